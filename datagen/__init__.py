@@ -25,6 +25,8 @@ __all__ = [
     "dense_planted_uniform",
     "dense_planted_halfnormal",
     "uniform_init",
+    "uniform_init_matched",
+    "mean_value",
     "bag_of_words",
     "bag_of_words_docs",
     "planted_separable",
@@ -111,6 +113,26 @@ def uniform_init(V: int, D: int, K: int, seed: int = 1):
     W = rng.random((V, K)).astype(np.float32)
     H = rng.random((K, D)).astype(np.float32)
     return W, H
+
+
+def mean_value(A) -> float:
+    """Mean entry of A (dense ndarray or Csr), zeros included."""
+    if isinstance(A, Csr):
+        return float(np.sum(A.val, dtype=np.float64)) / (A.rows * A.cols)
+    return float(np.mean(A, dtype=np.float64))
+
+
+def uniform_init_matched(V: int, D: int, K: int, a_mean: float, seed: int = 1):
+    """``uniform_init`` with H scaled so that the initial product matches the
+    data's mean entry in expectation: once W's U[0,1) columns are scaled to unit
+    norm (each by about sqrt(V/3)), E[(W H)_vd] = (K/4) h / sqrt(V/3), so
+    H ~ U[0,1) * h with h = a_mean * sqrt(V/3) / (K/4).  Same draws as
+    ``uniform_init``; the scale is applied in float64 before the FP32 rounding."""
+    rng = np.random.default_rng(seed)
+    W = rng.random((V, K))
+    H = rng.random((K, D))
+    h = a_mean * np.sqrt(V / 3.0) / (0.25 * K)
+    return W.astype(np.float32), (H * h).astype(np.float32)
 
 
 def planted_separable(V: int, D: int, K: int, seed: int, scale_lo: float = 0.5):

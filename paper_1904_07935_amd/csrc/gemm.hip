@@ -1,0 +1,435 @@
+// Matrix-core GEMM for gfx950: C = op(A) op(B) with FP32 accumulation.
+//
+// Used for every dense product of the sweep (A H^T and A^T W on dense A, Alg. 1
+// statements forming R and P), the Gram matrices W^T W and H H^T (the S and Q
+// statements of Alg. 1), the dense residual of the objective (Eq. 2), and the
+// warm-start network's forward and backward products.
+//
+// Tiles of 128 x 128 per workgroup, four wave64s in a 2 x 2 arrangement, each
+// owning 64 x 64 = 2 x 2 blocks of the 32 x 32 MFMA output.  Operands are staged
+// through double-buffered LDS in the layout each MFMA variant reads with
+// conflict-light unit-stride lane access:
+//   FP32  v_mfma_f32_32x32x2_f32   lane l supplies A[l%32][l/32], B[l/32][l%32]
+//         -> LDS k-major: As[k][m], Bs[k][n]; BK = 16
+//   BF16  v_mfma_f32_32x32x16_bf16 lane l supplies A[l%32][8(l/32)..+7] and
+//         B[8(l/32)..+7][l%32] -> LDS k-contiguous: As[m][k], Bs[n][k]; BK = 32
+// Output block layout (both): lane l holds C[8j + 4(l/32) + i][l%32], j,i < 4.
+// Split-K writes FP32 partials that a fixed-order pass sums (deterministic).
+#include "internal.hpp"
+
+namespace plnmf {
+namespace {
+
+constexpr int BM = 128, BN = 128;
+
+__device__ __forceinline__ float gelu_f(float z) {
+  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
+  float pdf = expf(-0.5f * z * z) * 0.39894228040143268f;
+  return cdf + z * pdf;
+}
+__device__ __forceinline__ float softplus_f(float z) {
+  return z > 20.0f ? z : log1pf(expf(z));
+}
+
+// Epilogue over one wave's 2 x 2 blocks.  `acc[i][j]` is the 32x32 block at
+// rows r0 + 32 i, cols c0 + 32 j.
+__device__ void epilogue(const GemmArgs& g, floatx16 (&acc)[2][2], int64_t r0, int64_t c0,
+                         double* red_smem) {
+  const int lane = threadIdx.x & 63;
+  double ss = 0.0;
+  const bool split = g.splits > 1;
+  float* out = split ? g.partial + (int64_t)blockIdx.z * g.M * g.N : g.C;
+  const int64_t ldo = split ? g.N : g.ldc;
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+        for (int ii = 0; ii < 4; ii++) {
+          const int64_t m = r0 + 32 * i + 8 * jj + 4 * (lane >> 5) + ii;
+          const int64_t n = c0 + 32 * j + (lane & 31);
+          if (m >= g.M || n >= g.N) continue;
+          float v = acc[i][j][jj * 4 + ii];
+          switch (g.epi) {
+            case EPI_STORE:
+              if (!split && g.bias) v += g.bias[n];
+              out[m * ldo + n] = v;
+              break;
+            case EPI_RESID_SQ: {
+              float e = g.D[m * g.ldd + n] - v;
+              ss += (double)e * (double)e;
+              break;
+            }
+            case EPI_BIAS_GELU: {
+              float z = v + g.bias[n];
+              g.C[m * g.ldc + n] = z;
+              ((__bf16*)g.C2)[m * g.ldc + n] = (__bf16)gelu_f(z);
+              break;
+            }
+            case EPI_BIAS_SOFTPLUS: {
+              float z = v + g.bias[n];
+              g.C[m * g.ldc + n] = z;
+              ((float*)g.C2)[m * g.ldc + n] = softplus_f(z);
+              break;
+            }
+            case EPI_GELU_GRAD: {
+              const float d = v * gelu_grad_f(g.D[m * g.ldd + n]);
+              if (g.C) g.C[m * g.ldc + n] = d;
+              ((__bf16*)g.C2)[m * g.ldc + n] = (__bf16)d;
+              break;
+            }
+          }
+        }
+  if (g.epi == EPI_RESID_SQ) {
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+    const int w = threadIdx.x >> 6;
+    if (lane == 0) red_smem[w] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = red_smem[0] + red_smem[1] + red_smem[2] + red_smem[3];
+      g.red_out[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- FP32 ----
+template <bool AT, bool BT, bool VEC>
+__global__ __launch_bounds__(256) void gemm_f32(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int LDS_A = BM + 4, LDS_B = BN + 4;
+  __shared__ float As[2][BK][LDS_A];
+  __shared__ float Bs[2][BK][LDS_B];
+  __shared__ double red[4];
+  const float* A = (const float*)g.A;
+  const float* B = (const float*)g.B;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  int64_t kb = 0, ke = g.Kd;
+  if (g.splits > 1) {
+    kb = (int64_t)blockIdx.z * g.k_per_split;
+    ke = kb + g.k_per_split < g.Kd ? kb + g.k_per_split : g.Kd;
+  }
+  const int nk = (int)((ke - kb + BK - 1) / BK);
+
+  floatx4 ra[2], rb[2];
+  float sa[8], sb[8];
+  auto load = [&](int kt) {
+    const int64_t k0 = kb + (int64_t)kt * BK;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int p = 0; p < 2; p++) {
+        const int idx = tid + 256 * p;
+        if constexpr (!AT) {  // along k
+          const int ml = idx >> 2, kq = idx & 3;
+          const int64_t m = m0 + ml, k = k0 + 4 * kq;
+          ra[p] = (m < g.M && k < ke) ? *(const floatx4*)(A + m * g.lda + k) : floatx4{0, 0, 0, 0};
+        } else {  // along m
+          const int kl = idx >> 5, mq = idx & 31;
+          const int64_t m = m0 + 4 * mq, k = k0 + kl;
+          ra[p] = (m < g.M && k < ke) ? *(const floatx4*)(A + k * g.lda + m) : floatx4{0, 0, 0, 0};
+        }
+        if constexpr (!BT) {  // along n
+          const int kl = idx >> 5, nq = idx & 31;
+          const int64_t n = n0 + 4 * nq, k = k0 + kl;
+          rb[p] = (n < g.N && k < ke) ? *(const floatx4*)(B + k * g.ldb + n) : floatx4{0, 0, 0, 0};
+        } else {  // along k
+          const int nl = idx >> 2, kq = idx & 3;
+          const int64_t n = n0 + nl, k = k0 + 4 * kq;
+          rb[p] = (n < g.N && k < ke) ? *(const floatx4*)(B + n * g.ldb + k) : floatx4{0, 0, 0, 0};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        const int idx = tid + 256 * e;           // element of the 128 x 16 tile
+        const int kl = idx & 15, ml = idx >> 4;  // k fastest
+        const int64_t k = k0 + kl;
+        const int64_t m = m0 + ml, n = n0 + ml;
+        sa[e] = (m < g.M && k < ke) ? (AT ? A[k * g.lda + m] : A[m * g.lda + k]) : 0.0f;
+        sb[e] = (n < g.N && k < ke) ? (BT ? B[n * g.ldb + k] : B[k * g.ldb + n]) : 0.0f;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    if constexpr (VEC) {
+#pragma unroll
+      for (int p = 0; p < 2; p++) {
+        const int idx = tid + 256 * p;
+        if constexpr (!AT) {
+          const int ml = idx >> 2, kq = idx & 3;
+#pragma unroll
+          for (int e = 0; e < 4; e++) As[buf][4 * kq + e][ml] = ra[p][e];
+        } else {
+          const int kl = idx >> 5, mq = idx & 31;
+          *(floatx4*)&As[buf][kl][4 * mq] = ra[p];
+        }
+        if constexpr (!BT) {
+          const int kl = idx >> 5, nq = idx & 31;
+          *(floatx4*)&Bs[buf][kl][4 * nq] = rb[p];
+        } else {
+          const int nl = idx >> 2, kq = idx & 3;
+#pragma unroll
+          for (int e = 0; e < 4; e++) Bs[buf][4 * kq + e][nl] = rb[p][e];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        const int idx = tid + 256 * e;
+        const int kl = idx & 15, ml = idx >> 4;
+        As[buf][kl][ml] = sa[e];
+        Bs[buf][kl][ml] = sb[e];
+      }
+    }
+  };
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+
+  if (nk > 0) {
+    load(0);
+    store(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; kt++) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      const int kr = kk + (lane >> 5);
+      const float a0 = As[buf][kr][wm * 64 + (lane & 31)];
+      const float a1 = As[buf][kr][wm * 64 + 32 + (lane & 31)];
+      const float b0 = Bs[buf][kr][wn * 64 + (lane & 31)];
+      const float b1 = Bs[buf][kr][wn * 64 + 32 + (lane & 31)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+  epilogue(g, acc, m0 + wm * 64, n0 + wn * 64, red);
+}
+
+// ---------------------------------------------------------------- BF16 ----
+template <bool AT, bool BT, bool VEC>
+__global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
+  constexpr int BK = 32;
+  constexpr int LDS_K = BK + 8;  // 80-byte rows keep 16-byte alignment
+  __shared__ __bf16 As[2][BM][LDS_K];
+  __shared__ __bf16 Bs[2][BN][LDS_K];
+  __shared__ double red[4];
+  const __bf16* A = (const __bf16*)g.A;
+  const __bf16* B = (const __bf16*)g.B;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  int64_t kb = 0, ke = g.Kd;
+  if (g.splits > 1) {
+    kb = (int64_t)blockIdx.z * g.k_per_split;
+    ke = kb + g.k_per_split < g.Kd ? kb + g.k_per_split : g.Kd;
+  }
+  const int nk = (int)((ke - kb + BK - 1) / BK);
+  const bf16x8 zero8 = {};
+
+  bf16x8 ra[2], rb[2];
+  __bf16 sa[16], sb[16];
+  auto load = [&](int kt) {
+    const int64_t k0 = kb + (int64_t)kt * BK;
+    if constexpr (VEC) {
+#pragma unroll
+      for (int p = 0; p < 2; p++) {
+        const int idx = tid + 256 * p;
+        if constexpr (!AT) {
+          const int ml = idx >> 2, kq = idx & 3;
+          const int64_t m = m0 + ml, k = k0 + 8 * kq;
+          ra[p] = (m < g.M && k < ke) ? *(const bf16x8*)(A + m * g.lda + k) : zero8;
+        } else {
+          const int kl = idx >> 4, mq = idx & 15;
+          const int64_t m = m0 + 8 * mq, k = k0 + kl;
+          ra[p] = (m < g.M && k < ke) ? *(const bf16x8*)(A + k * g.lda + m) : zero8;
+        }
+        if constexpr (!BT) {
+          const int kl = idx >> 4, nq = idx & 15;
+          const int64_t n = n0 + 8 * nq, k = k0 + kl;
+          rb[p] = (n < g.N && k < ke) ? *(const bf16x8*)(B + k * g.ldb + n) : zero8;
+        } else {
+          const int nl = idx >> 2, kq = idx & 3;
+          const int64_t n = n0 + nl, k = k0 + 8 * kq;
+          rb[p] = (n < g.N && k < ke) ? *(const bf16x8*)(B + n * g.ldb + k) : zero8;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; e++) {
+        const int idx = tid + 256 * e;           // element of the 128 x 32 tile
+        const int kl = idx & 31, ml = idx >> 5;  // k fastest
+        const int64_t k = k0 + kl;
+        const int64_t m = m0 + ml, n = n0 + ml;
+        sa[e] = (m < g.M && k < ke) ? (AT ? A[k * g.lda + m] : A[m * g.lda + k]) : (__bf16)0.0f;
+        sb[e] = (n < g.N && k < ke) ? (BT ? B[n * g.ldb + k] : B[k * g.ldb + n]) : (__bf16)0.0f;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+    if constexpr (VEC) {
+#pragma unroll
+      for (int p = 0; p < 2; p++) {
+        const int idx = tid + 256 * p;
+        if constexpr (!AT) {
+          const int ml = idx >> 2, kq = idx & 3;
+          *(bf16x8*)&As[buf][ml][8 * kq] = ra[p];
+        } else {
+          const int kl = idx >> 4, mq = idx & 15;
+#pragma unroll
+          for (int e = 0; e < 8; e++) As[buf][8 * mq + e][kl] = ra[p][e];
+        }
+        if constexpr (!BT) {
+          const int kl = idx >> 4, nq = idx & 15;
+#pragma unroll
+          for (int e = 0; e < 8; e++) Bs[buf][8 * nq + e][kl] = rb[p][e];
+        } else {
+          const int nl = idx >> 2, kq = idx & 3;
+          *(bf16x8*)&Bs[buf][nl][8 * kq] = rb[p];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; e++) {
+        const int idx = tid + 256 * e;
+        const int kl = idx & 31, ml = idx >> 5;
+        As[buf][ml][kl] = sa[e];
+        Bs[buf][ml][kl] = sb[e];
+      }
+    }
+  };
+
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+
+  if (nk > 0) {
+    load(0);
+    store(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; kt++) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int kc = kk + 8 * (lane >> 5);
+      const bf16x8 a0 = *(const bf16x8*)&As[buf][wm * 64 + (lane & 31)][kc];
+      const bf16x8 a1 = *(const bf16x8*)&As[buf][wm * 64 + 32 + (lane & 31)][kc];
+      const bf16x8 b0 = *(const bf16x8*)&Bs[buf][wn * 64 + (lane & 31)][kc];
+      const bf16x8 b1 = *(const bf16x8*)&Bs[buf][wn * 64 + 32 + (lane & 31)][kc];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+  epilogue(g, acc, m0 + wm * 64, n0 + wn * 64, red);
+}
+
+__global__ void splitk_reduce_kernel(const float* __restrict__ partial, int splits, int64_t M,
+                                     int64_t N, float* __restrict__ C, int64_t ldc,
+                                     const float* __restrict__ bias) {
+  const int64_t total = M * N;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int z = 0; z < splits; z++) s += partial[(int64_t)z * total + i];
+    const int64_t m = i / N, n = i - m * N;
+    if (bias) s += bias[n];
+    C[m * ldc + n] = s;
+  }
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+int gemm_pick_splits(int64_t M, int64_t N, int64_t Kd, int64_t* k_per_split) {
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int splits = 1;
+  // aim for >= 512 workgroups while every split keeps >= 256 of the contraction
+  while (tiles * splits < 512 && Kd / (splits * 2) >= 256 && splits < 256) splits *= 2;
+  int64_t kps = (Kd + splits - 1) / splits;
+  kps = (kps + 31) / 32 * 32;  // a multiple of both BK values
+  splits = (int)((Kd + kps - 1) / kps);
+  if (k_per_split) *k_per_split = kps;
+  return splits;
+}
+
+hipError_t splitk_reduce(const float* partial, int splits, int64_t M, int64_t N, float* C,
+                         int64_t ldc, const float* bias, hipStream_t s) {
+  const int64_t total = M * N;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  splitk_reduce_kernel<<<blocks, 256, 0, s>>>(partial, splits, M, N, C, ldc, bias);
+  return hipGetLastError();
+}
+
+hipError_t gemm(Elem t, bool a_trans, bool b_trans, const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  const int vw = t == Elem::F32 ? 4 : 8;
+  // vector path: the contiguous extent of each operand and its leading dim
+  // are multiples of the vector width, and the base is 16-byte aligned
+  const int64_t a_cont = a_trans ? g.M : g.Kd, b_cont = b_trans ? g.Kd : g.N;
+  const bool vec = aligned16(g.A) && aligned16(g.B) && g.lda % vw == 0 && g.ldb % vw == 0 &&
+                   a_cont % vw == 0 && b_cont % vw == 0 &&
+                   (g.splits <= 1 || g.k_per_split % vw == 0);
+  dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN),
+            (unsigned)(g.splits > 1 ? g.splits : 1));
+  const int code = (a_trans ? 4 : 0) | (b_trans ? 2 : 0) | (vec ? 1 : 0);
+  if (t == Elem::F32) {
+    switch (code) {
+      case 0: gemm_f32<false, false, false><<<grid, 256, 0, s>>>(g); break;
+      case 1: gemm_f32<false, false, true><<<grid, 256, 0, s>>>(g); break;
+      case 2: gemm_f32<false, true, false><<<grid, 256, 0, s>>>(g); break;
+      case 3: gemm_f32<false, true, true><<<grid, 256, 0, s>>>(g); break;
+      case 4: gemm_f32<true, false, false><<<grid, 256, 0, s>>>(g); break;
+      case 5: gemm_f32<true, false, true><<<grid, 256, 0, s>>>(g); break;
+      case 6: gemm_f32<true, true, false><<<grid, 256, 0, s>>>(g); break;
+      case 7: gemm_f32<true, true, true><<<grid, 256, 0, s>>>(g); break;
+    }
+  } else {
+    switch (code) {
+      case 0: gemm_bf16<false, false, false><<<grid, 256, 0, s>>>(g); break;
+      case 1: gemm_bf16<false, false, true><<<grid, 256, 0, s>>>(g); break;
+      case 2: gemm_bf16<false, true, false><<<grid, 256, 0, s>>>(g); break;
+      case 3: gemm_bf16<false, true, true><<<grid, 256, 0, s>>>(g); break;
+      case 4: gemm_bf16<true, false, false><<<grid, 256, 0, s>>>(g); break;
+      case 5: gemm_bf16<true, false, true><<<grid, 256, 0, s>>>(g); break;
+      case 6: gemm_bf16<true, true, false><<<grid, 256, 0, s>>>(g); break;
+      case 7: gemm_bf16<true, true, true><<<grid, 256, 0, s>>>(g); break;
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (g.splits > 1 && g.epi == EPI_STORE)
+    return splitk_reduce(g.partial, g.splits, g.M, g.N, g.C, g.ldc, g.bias, s);
+  return hipSuccess;
+}
+
+}  // namespace plnmf

@@ -1,0 +1,150 @@
+// Internal declarations shared by the host plan code and the kernel files.
+// Not part of the public ABI (include/nmf.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace plnmf {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxK = 512;
+constexpr int kTile = 32;          // tile width T of the column-update kernels
+constexpr int kSpinLimit = 1 << 21; // bounded waits: a few seconds of polling at most
+
+// ------------------------------------------------------------------ GEMM ----
+// C[M,N] = sum_k A(m,k) B(k,n) with FP32 accumulation on the matrix cores.
+// A(m,k) = A[m*lda + k] (a_trans = false) or A[k*lda + m] (a_trans = true);
+// B(k,n) = B[k*ldb + n] (b_trans = false) or B[n*ldb + k] (b_trans = true).
+enum GemmEpi : int {
+  EPI_STORE = 0,      // C = acc (+ bias[n])
+  EPI_RESID_SQ = 1,   // red_out[tile] = sum (D - acc)^2 over the tile (FP64)
+  EPI_BIAS_GELU = 2,  // C = acc + bias (pre-activation, FP32); C2 (bf16) = GELU(C)
+  EPI_BIAS_SOFTPLUS = 3, // C = acc + bias (FP32); C2 (float) = softplus(C)
+  EPI_GELU_GRAD = 4,  // C (FP32, if set) and C2 (bf16) = acc * GELU'(D), D = z1
+};
+
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  int64_t M, N, Kd;
+  int64_t lda, ldb;
+  float* C;
+  int64_t ldc;
+  int epi;
+  const float* bias;
+  const float* D;  // EPI_RESID_SQ: reference matrix; EPI_GELU_GRAD: z1
+  int64_t ldd;
+  void* C2;        // secondary output (ld = ldc)
+  double* red_out; // EPI_RESID_SQ partials, one per tile
+  int splits;      // split-K factor (EPI_STORE only); >1 needs `partial`
+  int64_t k_per_split;
+  float* partial;  // [splits][M][N]
+};
+
+enum class Elem { F32, BF16 };
+
+// Launch one GEMM.  Chooses tile/vector variants; returns hipError.
+hipError_t gemm(Elem t, bool a_trans, bool b_trans, const GemmArgs& g, hipStream_t s);
+// Pick a split-K factor and return partial-buffer floats needed (0 if none).
+int gemm_pick_splits(int64_t M, int64_t N, int64_t Kd, int64_t* k_per_split);
+// C[M,N] (ldc) = sum_z partial[z] (+ bias[n])
+hipError_t splitk_reduce(const float* partial, int splits, int64_t M, int64_t N, float* C,
+                         int64_t ldc, const float* bias, hipStream_t s);
+
+// ------------------------------------------------------------------ SpMM ----
+// out[r, 0:K] = sum_j val[j] X[col[j], 0:K] over the rows of a CSR matrix.
+// nnz is cut into chunks of `chunk` entries; rows crossing a chunk boundary are
+// finished by a fixed-order fixup pass over `carry` [nchunks][2][K].
+struct SpmmPlan {
+  int64_t rows, nnz;
+  int chunk;
+  int64_t nchunks;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const void* val;        // float or bf16 (elem)
+  const int32_t* chunk_row;  // [nchunks] row holding the chunk's first entry
+  const int32_t* fix_rows;   // rows that are split across chunks or empty
+  int64_t n_fix;
+  float* carry;            // [nchunks][2][K]
+};
+hipError_t spmm_build(SpmmPlan* p, int K, int32_t* chunk_row_buf, int32_t* fix_rows_buf,
+                      int32_t* counter, hipStream_t s);
+hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hipStream_t s);
+
+// CSR transpose (rows x cols -> cols x rows), deterministic, rows sorted.
+// scratch: int32 [nblk * cols] (nblk from csr_transpose_blocks).
+int csr_transpose_blocks(int64_t rows, int64_t cols, size_t scratch_ints);
+hipError_t csr_transpose(int64_t rows, int64_t cols, int64_t nnz, const int32_t* rowptr,
+                         const int32_t* col, const float* val, int32_t* t_rowptr, int32_t* t_col,
+                         float* t_val, int32_t* scratch, int nblk, hipStream_t s);
+// Structure check: sets flag bits (1 rowptr, 2 col range/order, 4 value) in *flag.
+hipError_t csr_validate(int64_t rows, int64_t cols, int64_t nnz, const int32_t* rowptr,
+                        const int32_t* col, const float* val, int32_t* flag, hipStream_t s);
+
+// ----------------------------------------------------------- elementwise ----
+hipError_t normalize_columns(float* X, int64_t rows, int K, double* part, int nblk_max,
+                             hipStream_t s);
+hipError_t cast_bf16(const float* x, __bf16* y, int64_t n, hipStream_t s);
+// y[c][r] = bf16(x[r][c]) for x [rows, cols]
+hipError_t cast_bf16_transpose(const float* x, __bf16* y, int64_t rows, int64_t cols,
+                               hipStream_t s);
+hipError_t check_finite_nonneg(const float* x, int64_t n, int32_t* flag, int bit, hipStream_t s);
+
+// FP64 fixed-order reductions.  partial buffers are [nblk] doubles.
+int reduce_blocks(int64_t n);
+hipError_t sumsq_f64(const float* x, int64_t n, double* partial, int nblk, hipStream_t s);
+hipError_t dot_f64(const float* x, const float* y, int64_t n, double* partial, int nblk,
+                   hipStream_t s);
+hipError_t finish_f64(const double* partial, int n, double* out, hipStream_t s);
+// out[0] = a2 + c1 * x[0] + c2 * y[0] ... combine for the sparse identity
+hipError_t combine_objective(const double* a2, const double* wp, const double* sq,
+                             double* out_half, double* out_rel, hipStream_t s);
+
+// --------------------------------------------------------- HALS updates ----
+// One tiled half-sweep over the rows of X [rows, K] (in place):
+//   acc[r,t] = Bterm[r,t] + X[r,t] * cdiag(t) - sum_{l != t} Xcur[r,l] G[l,t]
+//   X[r,t]   = max(eps, acc[r,t])       (NORM: then divided by the column norm)
+// cdiag = 1 - G[t,t] for the H update and 0 for the W update.
+struct HalsArgs {
+  float* X;
+  const float* Bterm;
+  const float* G;
+  int64_t rows;
+  int K;
+  float eps;
+  int diag_one;          // 1: H update (cdiag = 1 - G_tt); 0: W update
+  int rows_per_group;    // slab height
+  unsigned long long* slots;  // NORM: [2][groups] tagged partials
+  unsigned epoch;
+  int32_t* status;       // bit 8 set on a wait timeout
+};
+hipError_t hals_update(const HalsArgs& a, bool norm, int groups, hipStream_t s);
+int hals_w_groups(int64_t rows, int K, int device_cus);
+int hals_rows_per_group_h();
+int hals_w_max_coresident(int device_cus);
+
+// ----------------------------------------------------------------- MLP ----
+hipError_t mlp_init_params(float* master, int64_t n, int K, int hidden, uint64_t seed,
+                           hipStream_t s);
+hipError_t mlp_adam(float* master, float* m, float* v, const float* g, int64_t n, float lr,
+                    int64_t* step, hipStream_t s);
+hipError_t acc_scaled(double* acc, const double* v, double scale, hipStream_t s);
+hipError_t mlp_out_grad(const float* z2, const float* yhat, const float* y, int64_t n,
+                        float scale, __bf16* dz2_bf16, float* dz2_f32, double* loss_partial,
+                        int nblk, hipStream_t s);
+hipError_t col_sum(const float* x, int64_t rows, int64_t cols, float* out, hipStream_t s);
+
+hipError_t gather_rows(const float* x, const int32_t* idx, int64_t n, int64_t cols, float* out,
+                       hipStream_t s);
+hipError_t row_normalize(const float* x, int64_t rows, int64_t cols, float* xn, float* norms,
+                         hipStream_t s);
+hipError_t rescale_clip_rows(const float* y, const float* norms, int64_t rows, int64_t cols,
+                             float eps, float* out, hipStream_t s);
+hipError_t clip_min(const float* x, int64_t n, float eps, float* out, hipStream_t s);
+
+}  // namespace plnmf

@@ -1,0 +1,196 @@
+// Elementwise and reduction kernels around the sweep: the column normalisation
+// of W before the first sweep, BF16 operand casts, input checks, and the
+// fixed-order FP64 reductions of the objective (Eq. 2 and the relative
+// objective of Sec. 6.2).
+#include "internal.hpp"
+
+namespace plnmf {
+namespace {
+
+__device__ __forceinline__ double block_sum_d(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); i++) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+// partial[b][k] = sum over rows r = b, b + nblk, ... of X[r,k]^2 (FP64)
+__global__ void colsq_kernel(const float* __restrict__ X, int64_t rows, int K,
+                              double* __restrict__ part) {
+  const int b = blockIdx.x, nblk = gridDim.x;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double s = 0.0;
+    for (int64_t r = b; r < rows; r += nblk) {
+      const double x = X[r * K + k];
+      s += x * x;
+    }
+    part[(int64_t)b * K + k] = s;
+  }
+}
+
+__global__ void colscale(float* __restrict__ X, int64_t rows, int K, const double* __restrict__ part,
+                         int nblk) {
+  __shared__ float norm[kMaxK];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; b++) s += part[(int64_t)b * K + k];
+    norm[k] = (float)sqrt(s);
+  }
+  __syncthreads();
+  const int64_t n = rows * K;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i % K);
+    X[i] = X[i] / norm[k];
+  }
+}
+
+__global__ void cast_kernel(const float* __restrict__ x, __bf16* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (__bf16)x[i];
+}
+
+__global__ void cast_t_kernel(const float* __restrict__ x, __bf16* __restrict__ y, int64_t rows,
+                              int64_t cols) {
+  __shared__ float tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 256 threads: 8 rows per pass
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    tile[i][tx] = (r < rows && c < cols) ? x[r * cols + c] : 0.0f;
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < cols && r < rows) y[c * rows + r] = (__bf16)tile[tx][i];
+  }
+}
+
+__global__ void finite_nonneg(const float* __restrict__ x, int64_t n, int32_t* flag, int bit) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = x[i];
+    if (!(v >= 0.0f) || isinf(v)) bad = true;
+  }
+  if (bad) atomicOr(flag, bit);
+}
+
+__global__ void sumsq_kernel(const float* __restrict__ x, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[i];
+    s += v * v;
+  }
+  const double t = block_sum_d(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// sum of x*y over FP32 inputs, products and sums in FP64
+__global__ void dot_kernel(const float* __restrict__ x, const float* __restrict__ y, int64_t n,
+                           double* __restrict__ part) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)x[i] * (double)y[i];
+  const double t = block_sum_d(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void finish_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  // fixed assignment of partials to threads, then a fixed tree
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+  const double t = block_sum_d(s, sh);
+  if (threadIdx.x == 0) out[0] = t;
+}
+
+// out_half = e2 / 2, out_rel = sqrt(e2 / a2) with e2 = a2 - 2 wp + sq (identity)
+// or e2 = sq when wp is null (explicit residual)
+__global__ void combine_kernel(const double* a2, const double* wp, const double* sq,
+                               double* out_half, double* out_rel) {
+  double e2 = wp ? a2[0] - 2.0 * wp[0] + sq[0] : sq[0];
+  if (e2 < 0.0) e2 = 0.0;
+  out_half[0] = 0.5 * e2;
+  out_rel[0] = sqrt(e2 / a2[0]);
+}
+
+}  // namespace
+
+int reduce_blocks(int64_t n) {
+  int64_t b = (n + 4095) / 4096;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t normalize_columns(float* X, int64_t rows, int K, double* part, int nblk_max,
+                             hipStream_t s) {
+  int nblk = (int)((rows + 63) / 64);
+  if (nblk > nblk_max) nblk = nblk_max;
+  if (nblk < 1) nblk = 1;
+  colsq_kernel<<<nblk, 256, 0, s>>>(X, rows, K, part);
+  int gb = (int)((rows * K + 255) / 256);
+  if (gb > 2048) gb = 2048;
+  if (gb < 1) gb = 1;
+  colscale<<<gb, 256, 0, s>>>(X, rows, K, part, nblk);
+  return hipGetLastError();
+}
+
+static int grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t cast_bf16(const float* x, __bf16* y, int64_t n, hipStream_t s) {
+  cast_kernel<<<grid_for(n), 256, 0, s>>>(x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t cast_bf16_transpose(const float* x, __bf16* y, int64_t rows, int64_t cols,
+                               hipStream_t s) {
+  dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  cast_t_kernel<<<grid, 256, 0, s>>>(x, y, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t check_finite_nonneg(const float* x, int64_t n, int32_t* flag, int bit, hipStream_t s) {
+  finite_nonneg<<<grid_for(n), 256, 0, s>>>(x, n, flag, bit);
+  return hipGetLastError();
+}
+
+hipError_t sumsq_f64(const float* x, int64_t n, double* partial, int nblk, hipStream_t s) {
+  sumsq_kernel<<<nblk, 256, 0, s>>>(x, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t dot_f64(const float* x, const float* y, int64_t n, double* partial, int nblk,
+                   hipStream_t s) {
+  dot_kernel<<<nblk, 256, 0, s>>>(x, y, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t finish_f64(const double* partial, int n, double* out, hipStream_t s) {
+  finish_kernel<<<1, 256, 0, s>>>(partial, n, out);
+  return hipGetLastError();
+}
+
+hipError_t combine_objective(const double* a2, const double* wp, const double* sq,
+                             double* out_half, double* out_rel, hipStream_t s) {
+  combine_kernel<<<1, 1, 0, s>>>(a2, wp, sq, out_half, out_rel);
+  return hipGetLastError();
+}
+
+}  // namespace plnmf

@@ -1,0 +1,96 @@
+// Private host-side declarations shared by the C-ABI implementation files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/nmf.h"
+#include "internal.hpp"
+
+namespace plnmf {
+
+int fail(int code, const char* fmt, ...);
+
+#define HIPCHECK(plan, expr)                                                              \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      if (plan) (plan)->poisoned = NMF_E_HIP;                                             \
+      return ::plnmf::fail(NMF_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    }                                                                                     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Sequential carve of a workspace: with base == nullptr it only sizes.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int spmm_chunk_for(int64_t nnz);
+int device_check(int* dev, int* cus);
+int check_matrix(const nmf_matrix* A);
+
+}  // namespace plnmf
+
+struct nmf_plan_s {
+  int device = 0, cus = 0;
+  hipStream_t stream = nullptr;
+  int64_t V = 0, D = 0, nnz = 0;
+  int K = 0, fmt = 0, prec = 0;
+  float eps = 0.f;
+  float* W = nullptr;
+  float* Ht = nullptr;
+  const float* A_dense = nullptr;
+  const int32_t* a_rowptr = nullptr;
+  const int32_t* a_col = nullptr;
+  const float* a_val = nullptr;
+  int32_t* t_rowptr = nullptr;
+  int32_t* t_col = nullptr;
+  float* t_val = nullptr;
+  __bf16* a_val_bf = nullptr;
+  __bf16* t_val_bf = nullptr;
+  __bf16* A_bf = nullptr;   // dense [V,D]
+  __bf16* At_bf = nullptr;  // dense [D,V]
+  __bf16* X_bf = nullptr;   // per-sweep BF16 cast of W or Ht
+  plnmf::SpmmPlan sp_A{}, sp_At{};
+  plnmf::SpmmPlan sp_A_f32{};  // FP32 values of A (objective of BF16 plans)
+  float* P = nullptr;
+  float* Q = nullptr;
+  float* R = nullptr;
+  float* S = nullptr;
+  float* S2 = nullptr;
+  float* P2 = nullptr;      // FP32 A H^T for the objective of BF16 plans
+  float* partial = nullptr;
+  size_t partial_floats = 0;
+  double* colsq = nullptr;
+  double* red = nullptr;
+  int red_n = 0;
+  double* scal = nullptr;   // [0] ||A||^2 [1] <W,P> [2] sum sq [3] half [4] rel
+  unsigned long long* slots = nullptr;
+  int32_t* status = nullptr;
+  int w_groups = 0;
+  int w_rows_per_group = 0;
+  int tr_blocks = 1;
+  unsigned epoch = 1;
+  int64_t sweeps_done = 0;
+  bool pq_valid = false;
+  int poisoned = 0;
+};
+
+namespace plnmf {
+hipError_t gram(nmf_plan_s* p, const float* X, int64_t rows, float* out);
+int enqueue_objective(nmf_plan_s* p);
+}  // namespace plnmf

@@ -1,0 +1,131 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the
+header declares, sizes workspaces, and rejects bad arguments with the
+documented status codes (no device work is needed for any of these)."""
+import ctypes
+import os
+import re
+from ctypes import byref, c_size_t, c_void_p
+
+import pytest
+
+from paper_1904_07935_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nmf.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(nmf_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 20
+    h = ctypes.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(h, n), n
+    # and the binding covers exactly the declared entry points
+    assert set(L.SIGNATURES) | {"nmf_last_error"} == set(names)
+
+
+def _csr(rows=100, cols=80, nnz=500):
+    m = L.nmf_matrix()
+    m.rows, m.cols, m.nnz, m.format = rows, cols, nnz, L.NMF_CSR
+    m.rowptr = m.colidx = m.values = 0x1000
+    return m
+
+
+def _dense(rows=100, cols=80, ptr=0x1000):
+    m = L.nmf_matrix()
+    m.rows, m.cols, m.nnz, m.format = rows, cols, rows * cols, L.NMF_DENSE
+    m.dense = ptr
+    return m
+
+
+def test_workspace_sizes_grow_with_problem():
+    lib = L.lib()
+    b1, b2 = c_size_t(), c_size_t()
+    assert lib.nmf_workspace_bytes(byref(_dense(100, 80)), 8, L.NMF_FP32, byref(b1)) == 0
+    assert lib.nmf_workspace_bytes(byref(_dense(1000, 800)), 8, L.NMF_FP32, byref(b2)) == 0
+    assert b2.value > b1.value > 0
+    # BF16 products need extra BF16 copies of A
+    b3 = c_size_t()
+    assert lib.nmf_workspace_bytes(byref(_dense(1000, 800)), 8, L.NMF_BF16_PRODUCTS, byref(b3)) == 0
+    assert b3.value > b2.value
+    b4 = c_size_t()
+    assert lib.nmf_workspace_bytes(byref(_csr(26000, 11000, 858000)), 200, L.NMF_FP32, byref(b4)) == 0
+    # at least P, R and the transposed CSR
+    assert b4.value >= 4 * (26000 + 11000) * 200 + 8 * 858000
+
+
+@pytest.mark.parametrize("K,expect", [(0, L.NMF_E_SHAPE if hasattr(L, "NMF_E_SHAPE") else -2),
+                                      (81, -2), (513, -2), (80, 0), (1, 0)])
+def test_k_range(K, expect):
+    b = c_size_t()
+    assert L.lib().nmf_workspace_bytes(byref(_dense(100, 80)), K, L.NMF_FP32, byref(b)) == expect
+
+
+def test_bad_arguments():
+    lib = L.lib()
+    b = c_size_t()
+    assert lib.nmf_workspace_bytes(None, 4, 0, byref(b)) == -1
+    assert lib.nmf_workspace_bytes(byref(_dense()), 4, 7, byref(b)) == -1       # precision
+    assert lib.nmf_workspace_bytes(byref(_dense()), 4, 0, None) == -1
+    assert lib.nmf_workspace_bytes(byref(_dense(ptr=0x1004)), 4, 0, byref(b)) == -1  # alignment
+    m = _csr()
+    m.nnz = -1
+    assert lib.nmf_workspace_bytes(byref(m), 4, 0, byref(b)) == -2
+    m = _dense()
+    m.format = 9
+    assert lib.nmf_workspace_bytes(byref(m), 4, 0, byref(b)) == -1
+    assert b"format" in lib.nmf_last_error()
+
+
+def test_init_validation_before_device():
+    lib = L.lib()
+    h = c_void_p()
+    A = _dense()
+    b = c_size_t()
+    assert lib.nmf_workspace_bytes(byref(A), 4, 0, byref(b)) == 0
+    # eps must be > 0
+    assert lib.nmf_init(byref(h), byref(A), 4, 0.0, 0, 0x1000, 0x2000, 0x100000, b.value, None) == -1
+    assert lib.nmf_init(byref(h), byref(A), 4, float("inf"), 0, 0x1000, 0x2000, 0x100000, b.value,
+                        None) == -1
+    # misaligned factor / workspace
+    assert lib.nmf_init(byref(h), byref(A), 4, 1e-16, 0, 0x1004, 0x2000, 0x100000, b.value, None) == -1
+    assert lib.nmf_init(byref(h), byref(A), 4, 1e-16, 0, 0x1000, 0x2000, 0x100010, b.value, None) == -1
+    # undersized workspace
+    assert lib.nmf_init(byref(h), byref(A), 4, 1e-16, 0, 0x1000, 0x2000, 0x100000, b.value - 1,
+                        None) == -3
+    assert not h.value
+
+
+def test_null_plan_calls():
+    lib = L.lib()
+    assert lib.nmf_sweep(None, 1, None) == -1
+    assert lib.nmf_half(None, 0) == -1
+    assert lib.nmf_objective(None, None, None) == -1
+    assert lib.nmf_destroy(None) == 0
+
+
+def test_mlp_layout_and_bounds():
+    lay = L.nmf_mlp_layout()
+    assert L.lib().nmf_mlp_param_bytes(200, 512, byref(lay)) == 0
+    n = 512 * 200 * 2 + 512 + 200
+    assert lay.n_master == n
+    assert lay.adam_m >= 4 * n and lay.adam_v >= lay.adam_m + 4 * n
+    assert lay.w2_bf16 >= lay.w1_bf16 + 2 * 512 * 200
+    assert lay.total > lay.step
+    for off in (lay.adam_m, lay.adam_v, lay.w1_bf16, lay.w2_bf16, lay.step):
+        assert off % 256 == 0
+    assert L.lib().nmf_mlp_param_bytes(0, 512, byref(lay)) == -2
+    b = c_size_t()
+    assert L.lib().nmf_mlp_workspace_bytes(200, 512, 1024, byref(b)) == 0 and b.value > 0
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(L.NativeLibraryMissing):
+        L.lib()

@@ -43,3 +43,11 @@ def test_c1_size_matches_recipe():
     c = datagen.c1()
     assert (c.A.rows, c.A.cols) == (26000, 11000)
     assert 0.8e6 < c.A.nnz < 0.92e6  # about 0.3% dense
+
+
+def test_matched_init_scales_h_only():
+    W, H = datagen.uniform_init(300, 200, 10, seed=1)
+    Wm, Hm = datagen.uniform_init_matched(300, 200, 10, 0.5, seed=1)
+    assert np.array_equal(W, Wm)
+    h = 0.5 * np.sqrt(300 / 3.0) / 2.5
+    np.testing.assert_allclose(Hm, H.astype(np.float64) * h, rtol=1e-6)

@@ -1,0 +1,189 @@
+"""Parity of the HIP FAST-HALS path with the FP64 oracle (MI355X only).
+
+Bars (FP32 path): relative objective within 1e-5 (relative) of the oracle's
+after every sweep, and factors within 1e-3 (relative Frobenius) after 10
+sweeps, from the same FP32 inputs.  Single half-steps and products are held to
+tighter bounds derived from FP32 rounding of the sums involved."""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import hals
+from tests.gpu_util import EPS, gpu_plan, oracle_A, oracle_run, rel_fro, small_bow, sparse_init
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("V,D,K", [(130, 97, 7), (200, 150, 16), (97, 130, 33), (300, 260, 50),
+                                   (64, 64, 1), (40, 45, 40)])
+def test_products_grams_and_halves_dense(cuda, V, D, K):
+    A = datagen.dense_planted_uniform(V, D, max(2, K // 2), 0.01, seed=V + K)
+    W0, H0 = datagen.uniform_init(V, D, K, seed=K)
+    plan = gpu_plan(A, W0, H0, cuda)
+    Ao = oracle_A(A)
+    Wn = hals.normalize_columns(W0)
+    assert rel_fro(_np(plan.W), Wn) < 1e-6
+    plan.half("H")
+    mid = plan.intermediates()
+    H1, R, S = hals.h_half(Ao, Wn, H0, EPS)
+    assert rel_fro(_np(mid["R"]), R) < 1e-5
+    assert rel_fro(_np(mid["S"]), S) < 1e-5
+    assert rel_fro(_np(plan.Ht).T, H1) < 1e-4
+    plan.half("W")
+    mid = plan.intermediates()
+    W1, P, Q = hals.w_half(Ao, Wn, H1, EPS)
+    assert rel_fro(_np(mid["P"]), P) < 1e-4
+    assert rel_fro(_np(mid["Q"]), Q) < 1e-4
+    assert rel_fro(_np(plan.W), W1) < 1e-4
+    np.testing.assert_allclose(np.linalg.norm(_np(plan.W), axis=0), 1.0, rtol=1e-5)
+    assert _np(plan.Ht).min() >= EPS * (1 - 1e-6)
+    plan.close()
+
+
+def test_c0_parity_50_sweeps(cuda):
+    """The dense planted configuration: 1000 x 800, K = 16, 50 sweeps."""
+    A = datagen.c0()
+    W0, H0 = datagen.uniform_init(1000, 800, 16, seed=1)
+    plan = gpu_plan(A, W0, H0, cuda)
+    rel_gpu = []
+    for i in range(50):
+        rel_gpu += plan.sweep(1, objective=True)
+        if i == 9:
+            W10, Ht10 = _np(plan.W), _np(plan.Ht)
+    rel_or, facs = oracle_run(A, W0, H0, 50)
+    diffs = np.abs(np.array(rel_gpu) - np.array(rel_or)) / np.array(rel_or)
+    assert diffs.max() <= 1e-5, diffs
+    assert rel_fro(W10, facs[9][0]) <= 1e-3
+    assert rel_fro(Ht10.T, facs[9][1]) <= 1e-3
+    # objective is non-increasing (up to FP32 rounding) and matches the anchor values
+    assert np.all(np.diff(rel_gpu) <= 1e-6 * np.array(rel_gpu[1:]))
+    plan.close()
+
+
+@pytest.mark.parametrize("K", [5, 24, 64])
+def test_sparse_parity(cuda, K):
+    c = small_bow()
+    W0, H0 = sparse_init(c, K)
+    plan = gpu_plan(c.A, W0, H0, cuda)
+    rel_gpu = plan.sweep(10, objective=True)
+    rel_or, facs = oracle_run(c.A, W0, H0, 10)
+    diffs = np.abs(np.array(rel_gpu) - np.array(rel_or)) / np.array(rel_or)
+    assert diffs.max() <= 1e-5, diffs
+    assert rel_fro(_np(plan.W), facs[-1][0]) <= 1e-3
+    assert rel_fro(_np(plan.Ht).T, facs[-1][1]) <= 1e-3
+    plan.close()
+
+
+def test_sparse_products_with_empty_rows_and_columns(cuda):
+    """CSR with empty rows (terms never used) and empty columns (documents with
+    no terms) and one long row spanning many nnz chunks."""
+    rng = np.random.default_rng(5)
+    V, D, K = 700, 500, 12
+    dense = (rng.random((V, D)) < 0.02) * rng.random((V, D))
+    dense[3, :] = rng.random(D) + 0.1  # one long row (crosses chunk boundaries)
+    dense[::7, :] = 0.0          # empty rows
+    dense[:, ::11] = 0.0         # empty columns
+    import scipy.sparse as sp
+    m = sp.csr_matrix(dense.astype(np.float32))
+    A = datagen.Csr(V, D, m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.astype(np.float32))
+    W0, H0 = datagen.uniform_init(V, D, K, seed=1)
+    plan = gpu_plan(A, W0, H0, cuda)
+    Wn = hals.normalize_columns(W0)
+    Ao = oracle_A(A)
+    plan.half("H")
+    mid = plan.intermediates()
+    H1, R, S = hals.h_half(Ao, Wn, H0, EPS)
+    assert rel_fro(_np(mid["R"]), R) < 1e-5
+    assert np.all(_np(mid["R"])[::11] == 0.0)
+    plan.half("W")
+    mid = plan.intermediates()
+    _, P, _ = hals.w_half(Ao, Wn, H1, EPS)
+    assert rel_fro(_np(mid["P"]), P) < 1e-4
+    assert np.all(_np(mid["P"])[::7] == 0.0)
+    plan.close()
+
+
+def test_objective_matches_oracle(cuda):
+    A = datagen.dense_planted_uniform(300, 200, 8, 0.01, seed=3)
+    W0, H0 = datagen.uniform_init(300, 200, 8, seed=1)
+    plan = gpu_plan(A, W0, H0, cuda)
+    f, rel = plan.objective()
+    fo, relo = hals.objective(oracle_A(A), hals.normalize_columns(W0), H0.astype(np.float64))
+    assert abs(rel - relo) <= 1e-6 * relo and abs(f - fo) <= 2e-6 * fo
+    c = small_bow(1500, 700)
+    W0, H0 = sparse_init(c, 10)
+    plan2 = gpu_plan(c.A, W0, H0, cuda)
+    f, rel = plan2.objective()
+    fo, relo = hals.objective(oracle_A(c.A), hals.normalize_columns(W0), H0.astype(np.float64))
+    assert abs(rel - relo) <= 1e-5 * relo
+    plan.close()
+    plan2.close()
+
+
+def test_bitwise_deterministic_and_resumable(cuda):
+    import torch
+    c = small_bow(2000, 900)
+    W0, H0 = sparse_init(c, 20)
+    p1 = gpu_plan(c.A, W0, H0, cuda)
+    p2 = gpu_plan(c.A, W0, H0, cuda)
+    p1.sweep(6)
+    p2.sweep(3)
+    Ws, Hs = p2.W.clone(), p2.Ht.clone()
+    p2.sweep(3)
+    assert torch.equal(p1.W, p2.W) and torch.equal(p1.Ht, p2.Ht)
+    p2.W.copy_(Ws)
+    p2.Ht.copy_(Hs)
+    p2.sweep(3)  # continue from the saved state
+    assert torch.equal(p1.W, p2.W) and torch.equal(p1.Ht, p2.Ht)
+    p1.close()
+    p2.close()
+
+
+def test_dead_column_becomes_uniform(cuda):
+    """A W column whose update is <= eps in every row becomes 1/sqrt(V)."""
+    V, D, K = 64, 48, 3
+    rng = np.random.default_rng(0)
+    A = np.zeros((V, D), dtype=np.float32)
+    A[:, :] = rng.random((V, D)).astype(np.float32) * 0.1
+    W0 = rng.random((V, K)).astype(np.float32)
+    H0 = rng.random((K, D)).astype(np.float32)
+    H0[1, :] = 50.0  # row 1 of H far too large: column 1 of W clips everywhere
+    plan = gpu_plan(A, W0, H0, cuda)
+    # run only the W half on the given H
+    plan.half("W")
+    Wo, _, _ = hals.w_half(A.astype(np.float64), hals.normalize_columns(W0), H0.astype(np.float64), EPS)
+    got = _np(plan.W)
+    assert rel_fro(got, Wo) < 1e-4
+    plan.close()
+
+
+def test_input_validation_on_device(cuda):
+    import torch
+
+    from paper_1904_07935_amd._lib import NmfError
+    from paper_1904_07935_amd.api import Matrix, Plan
+    V, D, K = 50, 40, 4
+    W = torch.rand(V, K, device=cuda)
+    Ht = torch.rand(D, K, device=cuda)
+    A = torch.rand(V, D, device=cuda)
+    A[3, 4] = -1.0
+    with pytest.raises(NmfError) as e:
+        Plan(Matrix(V, D, dense=A), W, Ht)
+    assert e.value.status == -5
+    A[3, 4] = 1.0
+    W[0, 0] = float("nan")
+    with pytest.raises(NmfError) as e:
+        Plan(Matrix(V, D, dense=A), W.clone(), Ht)
+    assert e.value.status == -5
+    # unsorted CSR columns
+    rp = torch.tensor([0, 2, 3], dtype=torch.int32, device=cuda)
+    cl = torch.tensor([3, 1, 0], dtype=torch.int32, device=cuda)
+    vl = torch.ones(3, device=cuda)
+    with pytest.raises(NmfError) as e:
+        Plan(Matrix(2, 5, rowptr=rp, col=cl, val=vl), torch.rand(2, 1, device=cuda),
+             torch.rand(5, 1, device=cuda))
+    assert e.value.status == -2
