@@ -95,6 +95,7 @@ hipError_t gram_with(const float* X, int64_t rows, int K, float* out, float* par
   g.epi = EPI_STORE;
   g.splits = gemm_pick_splits(g.M, g.N, g.Kd, &g.k_per_split);
   g.partial = partial;
+  g.sym = 1;
   return gemm(Elem::F32, true, false, g, s);
 }
 

@@ -15,6 +15,8 @@
 //         B[8(l/32)..+7][l%32] -> LDS k-contiguous: As[m][k], Bs[n][k]; BK = 32
 // Output block layout (both): lane l holds C[8j + 4(l/32) + i][l%32], j,i < 4.
 // Split-K writes FP32 partials that a fixed-order pass sums (deterministic).
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace plnmf {
@@ -35,14 +37,17 @@ __device__ __forceinline__ float softplus_f(float z) {
 }
 
 // Epilogue over one wave's 2 x 2 blocks.  `acc[i][j]` is the 32x32 block at
-// rows r0 + 32 i, cols c0 + 32 j.
-__device__ void epilogue(const GemmArgs& g, floatx16 (&acc)[2][2], int64_t r0, int64_t c0,
-                         double* red_smem) {
+// rows r0 + 32 i, cols c0 + 32 j.  Every field is passed by value so nothing
+// here takes the address of the kernel argument block.
+__device__ __forceinline__ void epilogue(int epi, int64_t M, int64_t N, float* __restrict__ out,
+                                         int64_t ldo, bool split, const float* __restrict__ bias,
+                                         const float* __restrict__ Dm, int64_t ldd,
+                                         void* __restrict__ C2, float* __restrict__ C,
+                                         int64_t ldc, double* __restrict__ red_out,
+                                         floatx16 (&acc)[2][2], int64_t r0, int64_t c0,
+                                         double* red_smem, bool mirror) {
   const int lane = threadIdx.x & 63;
   double ss = 0.0;
-  const bool split = g.splits > 1;
-  float* out = split ? g.partial + (int64_t)blockIdx.z * g.M * g.N : g.C;
-  const int64_t ldo = split ? g.N : g.ldc;
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
@@ -53,74 +58,54 @@ __device__ void epilogue(const GemmArgs& g, floatx16 (&acc)[2][2], int64_t r0, i
         for (int ii = 0; ii < 4; ii++) {
           const int64_t m = r0 + 32 * i + 8 * jj + 4 * (lane >> 5) + ii;
           const int64_t n = c0 + 32 * j + (lane & 31);
-          if (m >= g.M || n >= g.N) continue;
+          if (m >= M || n >= N) continue;
           float v = acc[i][j][jj * 4 + ii];
-          switch (g.epi) {
-            case EPI_STORE:
-              if (!split && g.bias) v += g.bias[n];
-              out[m * ldo + n] = v;
-              break;
-            case EPI_RESID_SQ: {
-              float e = g.D[m * g.ldd + n] - v;
-              ss += (double)e * (double)e;
-              break;
-            }
-            case EPI_BIAS_GELU: {
-              float z = v + g.bias[n];
-              g.C[m * g.ldc + n] = z;
-              ((__bf16*)g.C2)[m * g.ldc + n] = (__bf16)gelu_f(z);
-              break;
-            }
-            case EPI_BIAS_SOFTPLUS: {
-              float z = v + g.bias[n];
-              g.C[m * g.ldc + n] = z;
-              ((float*)g.C2)[m * g.ldc + n] = softplus_f(z);
-              break;
-            }
-            case EPI_GELU_GRAD: {
-              const float d = v * gelu_grad_f(g.D[m * g.ldd + n]);
-              if (g.C) g.C[m * g.ldc + n] = d;
-              ((__bf16*)g.C2)[m * g.ldc + n] = (__bf16)d;
-              break;
-            }
+          if (epi == EPI_STORE) {
+            if (!split && bias) v += bias[n];
+            out[m * ldo + n] = v;
+            if (mirror) out[n * ldo + m] = v;  // symmetric product, tile above the diagonal
+          } else if (epi == EPI_RESID_SQ) {
+            const float e = Dm[m * ldd + n] - v;
+            ss += (double)e * (double)e;
+          } else if (epi == EPI_BIAS_GELU) {
+            const float z = v + bias[n];
+            C[m * ldc + n] = z;
+            ((__bf16*)C2)[m * ldc + n] = (__bf16)gelu_f(z);
+          } else if (epi == EPI_BIAS_SOFTPLUS) {
+            const float z = v + bias[n];
+            C[m * ldc + n] = z;
+            ((float*)C2)[m * ldc + n] = softplus_f(z);
+          } else if (epi == EPI_GELU_GRAD) {
+            const float d = v * gelu_grad_f(Dm[m * ldd + n]);
+            if (C) C[m * ldc + n] = d;
+            ((__bf16*)C2)[m * ldc + n] = (__bf16)d;
           }
         }
-  if (g.epi == EPI_RESID_SQ) {
+  if (epi == EPI_RESID_SQ) {
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
     const int w = threadIdx.x >> 6;
     if (lane == 0) red_smem[w] = ss;
     __syncthreads();
     if (threadIdx.x == 0) {
-      double t = red_smem[0] + red_smem[1] + red_smem[2] + red_smem[3];
-      g.red_out[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+      const double t = red_smem[0] + red_smem[1] + red_smem[2] + red_smem[3];
+      red_out[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
     }
   }
 }
 
-// ---------------------------------------------------------------- FP32 ----
-template <bool AT, bool BT, bool VEC>
-__global__ __launch_bounds__(256) void gemm_f32(GemmArgs g) {
-  constexpr int BK = 16;
-  constexpr int LDS_A = BM + 4, LDS_B = BN + 4;
-  __shared__ float As[2][BK][LDS_A];
-  __shared__ float Bs[2][BK][LDS_B];
-  __shared__ double red[4];
-  const float* A = (const float*)g.A;
-  const float* B = (const float*)g.B;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
-  int64_t kb = 0, ke = g.Kd;
-  if (g.splits > 1) {
-    kb = (int64_t)blockIdx.z * g.k_per_split;
-    ke = kb + g.k_per_split < g.Kd ? kb + g.k_per_split : g.Kd;
-  }
-  const int nk = (int)((ke - kb + BK - 1) / BK);
+// Global -> register -> LDS staging of one K-step of the A and B tiles.
+template <typename T, bool AT, bool BT, bool VEC, int BK>
+struct Stage;
 
+// FP32: As[k][m], Bs[k][n] (k-major), BK = 16
+template <bool AT, bool BT, bool VEC>
+struct Stage<float, AT, BT, VEC, 16> {
+  static constexpr int LDS_A = BM + 4, LDS_B = BN + 4;
   floatx4 ra[2], rb[2];
   float sa[8], sb[8];
-  auto load = [&](int kt) {
-    const int64_t k0 = kb + (int64_t)kt * BK;
+  __device__ __forceinline__ void load(const float* __restrict__ A, const float* __restrict__ B,
+                                       int64_t lda, int64_t ldb, int64_t M, int64_t N,
+                                       int64_t m0, int64_t n0, int64_t k0, int64_t ke, int tid) {
     if constexpr (VEC) {
 #pragma unroll
       for (int p = 0; p < 2; p++) {
@@ -128,20 +113,20 @@ __global__ __launch_bounds__(256) void gemm_f32(GemmArgs g) {
         if constexpr (!AT) {  // along k
           const int ml = idx >> 2, kq = idx & 3;
           const int64_t m = m0 + ml, k = k0 + 4 * kq;
-          ra[p] = (m < g.M && k < ke) ? *(const floatx4*)(A + m * g.lda + k) : floatx4{0, 0, 0, 0};
+          ra[p] = (m < M && k < ke) ? *(const floatx4*)(A + m * lda + k) : floatx4{0, 0, 0, 0};
         } else {  // along m
           const int kl = idx >> 5, mq = idx & 31;
           const int64_t m = m0 + 4 * mq, k = k0 + kl;
-          ra[p] = (m < g.M && k < ke) ? *(const floatx4*)(A + k * g.lda + m) : floatx4{0, 0, 0, 0};
+          ra[p] = (m < M && k < ke) ? *(const floatx4*)(A + k * lda + m) : floatx4{0, 0, 0, 0};
         }
         if constexpr (!BT) {  // along n
           const int kl = idx >> 5, nq = idx & 31;
           const int64_t n = n0 + 4 * nq, k = k0 + kl;
-          rb[p] = (n < g.N && k < ke) ? *(const floatx4*)(B + k * g.ldb + n) : floatx4{0, 0, 0, 0};
+          rb[p] = (n < N && k < ke) ? *(const floatx4*)(B + k * ldb + n) : floatx4{0, 0, 0, 0};
         } else {  // along k
           const int nl = idx >> 2, kq = idx & 3;
           const int64_t n = n0 + nl, k = k0 + 4 * kq;
-          rb[p] = (n < g.N && k < ke) ? *(const floatx4*)(B + n * g.ldb + k) : floatx4{0, 0, 0, 0};
+          rb[p] = (n < N && k < ke) ? *(const floatx4*)(B + n * ldb + k) : floatx4{0, 0, 0, 0};
         }
       }
     } else {
@@ -151,12 +136,12 @@ __global__ __launch_bounds__(256) void gemm_f32(GemmArgs g) {
         const int kl = idx & 15, ml = idx >> 4;  // k fastest
         const int64_t k = k0 + kl;
         const int64_t m = m0 + ml, n = n0 + ml;
-        sa[e] = (m < g.M && k < ke) ? (AT ? A[k * g.lda + m] : A[m * g.lda + k]) : 0.0f;
-        sb[e] = (n < g.N && k < ke) ? (BT ? B[n * g.ldb + k] : B[k * g.ldb + n]) : 0.0f;
+        sa[e] = (m < M && k < ke) ? (AT ? A[k * lda + m] : A[m * lda + k]) : 0.0f;
+        sb[e] = (n < N && k < ke) ? (BT ? B[n * ldb + k] : B[k * ldb + n]) : 0.0f;
       }
     }
-  };
-  auto store = [&](int buf) {
+  }
+  __device__ __forceinline__ void store(float (*As)[LDS_A], float (*Bs)[LDS_B], int tid) {
     if constexpr (VEC) {
 #pragma unroll
       for (int p = 0; p < 2; p++) {
@@ -164,18 +149,18 @@ __global__ __launch_bounds__(256) void gemm_f32(GemmArgs g) {
         if constexpr (!AT) {
           const int ml = idx >> 2, kq = idx & 3;
 #pragma unroll
-          for (int e = 0; e < 4; e++) As[buf][4 * kq + e][ml] = ra[p][e];
+          for (int e = 0; e < 4; e++) As[4 * kq + e][ml] = ra[p][e];
         } else {
           const int kl = idx >> 5, mq = idx & 31;
-          *(floatx4*)&As[buf][kl][4 * mq] = ra[p];
+          *(floatx4*)&As[kl][4 * mq] = ra[p];
         }
         if constexpr (!BT) {
           const int kl = idx >> 5, nq = idx & 31;
-          *(floatx4*)&Bs[buf][kl][4 * nq] = rb[p];
+          *(floatx4*)&Bs[kl][4 * nq] = rb[p];
         } else {
           const int nl = idx >> 2, kq = idx & 3;
 #pragma unroll
-          for (int e = 0; e < 4; e++) Bs[buf][4 * kq + e][nl] = rb[p][e];
+          for (int e = 0; e < 4; e++) Bs[4 * kq + e][nl] = rb[p][e];
         }
       }
     } else {
@@ -183,71 +168,23 @@ __global__ __launch_bounds__(256) void gemm_f32(GemmArgs g) {
       for (int e = 0; e < 8; e++) {
         const int idx = tid + 256 * e;
         const int kl = idx & 15, ml = idx >> 4;
-        As[buf][kl][ml] = sa[e];
-        Bs[buf][kl][ml] = sb[e];
+        As[kl][ml] = sa[e];
+        Bs[kl][ml] = sb[e];
       }
     }
-  };
-
-  floatx16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++)
-#pragma unroll
-      for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
-
-  if (nk > 0) {
-    load(0);
-    store(0);
-    __syncthreads();
   }
-  for (int kt = 0; kt < nk; kt++) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load(kt + 1);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 2) {
-      const int kr = kk + (lane >> 5);
-      const float a0 = As[buf][kr][wm * 64 + (lane & 31)];
-      const float a1 = As[buf][kr][wm * 64 + 32 + (lane & 31)];
-      const float b0 = Bs[buf][kr][wn * 64 + (lane & 31)];
-      const float b1 = Bs[buf][kr][wn * 64 + 32 + (lane & 31)];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
-    }
-    if (kt + 1 < nk) store(buf ^ 1);
-    __syncthreads();
-  }
-  epilogue(g, acc, m0 + wm * 64, n0 + wn * 64, red);
-}
+};
 
-// ---------------------------------------------------------------- BF16 ----
+// BF16: As[m][k], Bs[n][k] (k-contiguous), BK = 32
 template <bool AT, bool BT, bool VEC>
-__global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
-  constexpr int BK = 32;
-  constexpr int LDS_K = BK + 8;  // 80-byte rows keep 16-byte alignment
-  __shared__ __bf16 As[2][BM][LDS_K];
-  __shared__ __bf16 Bs[2][BN][LDS_K];
-  __shared__ double red[4];
-  const __bf16* A = (const __bf16*)g.A;
-  const __bf16* B = (const __bf16*)g.B;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
-  int64_t kb = 0, ke = g.Kd;
-  if (g.splits > 1) {
-    kb = (int64_t)blockIdx.z * g.k_per_split;
-    ke = kb + g.k_per_split < g.Kd ? kb + g.k_per_split : g.Kd;
-  }
-  const int nk = (int)((ke - kb + BK - 1) / BK);
-  const bf16x8 zero8 = {};
-
+struct Stage<__bf16, AT, BT, VEC, 32> {
+  static constexpr int LDS_K = 32 + 8;  // 80-byte rows keep 16-byte alignment
   bf16x8 ra[2], rb[2];
   __bf16 sa[16], sb[16];
-  auto load = [&](int kt) {
-    const int64_t k0 = kb + (int64_t)kt * BK;
+  __device__ __forceinline__ void load(const __bf16* __restrict__ A, const __bf16* __restrict__ B,
+                                       int64_t lda, int64_t ldb, int64_t M, int64_t N,
+                                       int64_t m0, int64_t n0, int64_t k0, int64_t ke, int tid) {
+    const bf16x8 zero8 = {};
     if constexpr (VEC) {
 #pragma unroll
       for (int p = 0; p < 2; p++) {
@@ -255,20 +192,20 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
         if constexpr (!AT) {
           const int ml = idx >> 2, kq = idx & 3;
           const int64_t m = m0 + ml, k = k0 + 8 * kq;
-          ra[p] = (m < g.M && k < ke) ? *(const bf16x8*)(A + m * g.lda + k) : zero8;
+          ra[p] = (m < M && k < ke) ? *(const bf16x8*)(A + m * lda + k) : zero8;
         } else {
           const int kl = idx >> 4, mq = idx & 15;
           const int64_t m = m0 + 8 * mq, k = k0 + kl;
-          ra[p] = (m < g.M && k < ke) ? *(const bf16x8*)(A + k * g.lda + m) : zero8;
+          ra[p] = (m < M && k < ke) ? *(const bf16x8*)(A + k * lda + m) : zero8;
         }
         if constexpr (!BT) {
           const int kl = idx >> 4, nq = idx & 15;
           const int64_t n = n0 + 8 * nq, k = k0 + kl;
-          rb[p] = (n < g.N && k < ke) ? *(const bf16x8*)(B + k * g.ldb + n) : zero8;
+          rb[p] = (n < N && k < ke) ? *(const bf16x8*)(B + k * ldb + n) : zero8;
         } else {
           const int nl = idx >> 2, kq = idx & 3;
           const int64_t n = n0 + nl, k = k0 + 8 * kq;
-          rb[p] = (n < g.N && k < ke) ? *(const bf16x8*)(B + n * g.ldb + k) : zero8;
+          rb[p] = (n < N && k < ke) ? *(const bf16x8*)(B + n * ldb + k) : zero8;
         }
       }
     } else {
@@ -278,31 +215,31 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
         const int kl = idx & 31, ml = idx >> 5;  // k fastest
         const int64_t k = k0 + kl;
         const int64_t m = m0 + ml, n = n0 + ml;
-        sa[e] = (m < g.M && k < ke) ? (AT ? A[k * g.lda + m] : A[m * g.lda + k]) : (__bf16)0.0f;
-        sb[e] = (n < g.N && k < ke) ? (BT ? B[n * g.ldb + k] : B[k * g.ldb + n]) : (__bf16)0.0f;
+        sa[e] = (m < M && k < ke) ? (AT ? A[k * lda + m] : A[m * lda + k]) : (__bf16)0.0f;
+        sb[e] = (n < N && k < ke) ? (BT ? B[n * ldb + k] : B[k * ldb + n]) : (__bf16)0.0f;
       }
     }
-  };
-  auto store = [&](int buf) {
+  }
+  __device__ __forceinline__ void store(__bf16 (*As)[LDS_K], __bf16 (*Bs)[LDS_K], int tid) {
     if constexpr (VEC) {
 #pragma unroll
       for (int p = 0; p < 2; p++) {
         const int idx = tid + 256 * p;
         if constexpr (!AT) {
           const int ml = idx >> 2, kq = idx & 3;
-          *(bf16x8*)&As[buf][ml][8 * kq] = ra[p];
+          *(bf16x8*)&As[ml][8 * kq] = ra[p];
         } else {
           const int kl = idx >> 4, mq = idx & 15;
 #pragma unroll
-          for (int e = 0; e < 8; e++) As[buf][8 * mq + e][kl] = ra[p][e];
+          for (int e = 0; e < 8; e++) As[8 * mq + e][kl] = ra[p][e];
         }
         if constexpr (!BT) {
           const int kl = idx >> 4, nq = idx & 15;
 #pragma unroll
-          for (int e = 0; e < 8; e++) Bs[buf][8 * nq + e][kl] = rb[p][e];
+          for (int e = 0; e < 8; e++) Bs[8 * nq + e][kl] = rb[p][e];
         } else {
           const int nl = idx >> 2, kq = idx & 3;
-          *(bf16x8*)&Bs[buf][nl][8 * kq] = rb[p];
+          *(bf16x8*)&Bs[nl][8 * kq] = rb[p];
         }
       }
     } else {
@@ -310,12 +247,79 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
       for (int e = 0; e < 16; e++) {
         const int idx = tid + 256 * e;
         const int kl = idx & 31, ml = idx >> 5;
-        As[buf][ml][kl] = sa[e];
-        Bs[buf][ml][kl] = sb[e];
+        As[ml][kl] = sa[e];
+        Bs[ml][kl] = sb[e];
       }
     }
-  };
+  }
+};
 
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  static constexpr int BK = 16;
+  // one K-step of 2 on the four 32x32 blocks of this wave
+  template <typename AS, typename BS>
+  __device__ __forceinline__ static void step(AS As, BS Bs, floatx16 (&acc)[2][2], int wm, int wn,
+                                              int lane) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      const int kr = kk + (lane >> 5);
+      const float a0 = As[kr][wm * 64 + (lane & 31)];
+      const float a1 = As[kr][wm * 64 + 32 + (lane & 31)];
+      const float b0 = Bs[kr][wn * 64 + (lane & 31)];
+      const float b1 = Bs[kr][wn * 64 + 32 + (lane & 31)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+};
+template <>
+struct Mfma<__bf16> {
+  static constexpr int BK = 32;
+  template <typename AS, typename BS>
+  __device__ __forceinline__ static void step(AS As, BS Bs, floatx16 (&acc)[2][2], int wm, int wn,
+                                              int lane) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int kc = kk + 8 * (lane >> 5);
+      const bf16x8 a0 = *(const bf16x8*)&As[wm * 64 + (lane & 31)][kc];
+      const bf16x8 a1 = *(const bf16x8*)&As[wm * 64 + 32 + (lane & 31)][kc];
+      const bf16x8 b0 = *(const bf16x8*)&Bs[wn * 64 + (lane & 31)][kc];
+      const bf16x8 b1 = *(const bf16x8*)&Bs[wn * 64 + 32 + (lane & 31)][kc];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+};
+
+template <typename T, bool AT, bool BT, bool VEC>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
+  constexpr int BK = Mfma<T>::BK;
+  using St = Stage<T, AT, BT, VEC, BK>;
+  // scalar copies of the argument block (keeps its address untaken)
+  const T* __restrict__ A = (const T*)g.A;
+  const T* __restrict__ B = (const T*)g.B;
+  const int64_t M = g.M, N = g.N, Kd = g.Kd, lda = g.lda, ldb = g.ldb;
+  const int splits = g.splits;
+  const int64_t kps = g.k_per_split;
+  const int sym = g.sym;
+  if (sym && blockIdx.y < blockIdx.x) return;  // symmetric product: upper tiles only
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  int64_t kb = 0, ke = Kd;
+  if (splits > 1) {
+    kb = (int64_t)blockIdx.z * kps;
+    ke = kb + kps < Kd ? kb + kps : Kd;
+  }
+  const int nk = (int)((ke - kb + BK - 1) / BK);
+  __shared__ double red[4];
   floatx16 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; i++)
@@ -324,41 +328,57 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
 #pragma unroll
       for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
 
-  if (nk > 0) {
-    load(0);
-    store(0);
-    __syncthreads();
-  }
-  for (int kt = 0; kt < nk; kt++) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load(kt + 1);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 16) {
-      const int kc = kk + 8 * (lane >> 5);
-      const bf16x8 a0 = *(const bf16x8*)&As[buf][wm * 64 + (lane & 31)][kc];
-      const bf16x8 a1 = *(const bf16x8*)&As[buf][wm * 64 + 32 + (lane & 31)][kc];
-      const bf16x8 b0 = *(const bf16x8*)&Bs[buf][wn * 64 + (lane & 31)][kc];
-      const bf16x8 b1 = *(const bf16x8*)&Bs[buf][wn * 64 + 32 + (lane & 31)][kc];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+  if constexpr (std::is_same<T, float>::value) {
+    __shared__ float As[2][BK][St::LDS_A];
+    __shared__ float Bs[2][BK][St::LDS_B];
+    St st;
+    if (nk > 0) {
+      st.load(A, B, lda, ldb, M, N, m0, n0, kb, ke, tid);
+      st.store(As[0], Bs[0], tid);
+      __syncthreads();
     }
-    if (kt + 1 < nk) store(buf ^ 1);
-    __syncthreads();
+    for (int kt = 0; kt < nk; kt++) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) st.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 1) * BK, ke, tid);
+      Mfma<T>::step(As[buf], Bs[buf], acc, wm, wn, lane);
+      if (kt + 1 < nk) st.store(As[buf ^ 1], Bs[buf ^ 1], tid);
+      __syncthreads();
+    }
+  } else {
+    __shared__ __bf16 As[2][BM][St::LDS_K];
+    __shared__ __bf16 Bs[2][BN][St::LDS_K];
+    St st;
+    if (nk > 0) {
+      st.load(A, B, lda, ldb, M, N, m0, n0, kb, ke, tid);
+      st.store(As[0], Bs[0], tid);
+      __syncthreads();
+    }
+    for (int kt = 0; kt < nk; kt++) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) st.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 1) * BK, ke, tid);
+      Mfma<T>::step(As[buf], Bs[buf], acc, wm, wn, lane);
+      if (kt + 1 < nk) st.store(As[buf ^ 1], Bs[buf ^ 1], tid);
+      __syncthreads();
+    }
   }
-  epilogue(g, acc, m0 + wm * 64, n0 + wn * 64, red);
+  const bool split = splits > 1;
+  float* out = split ? g.partial + (int64_t)blockIdx.z * M * N : g.C;
+  epilogue(g.epi, M, N, out, split ? N : g.ldc, split, g.bias, g.D, g.ldd, g.C2, g.C, g.ldc,
+           g.red_out, acc, m0 + wm * 64, n0 + wn * 64, red,
+           sym && !split && blockIdx.y != blockIdx.x);
 }
 
 __global__ void splitk_reduce_kernel(const float* __restrict__ partial, int splits, int64_t M,
                                      int64_t N, float* __restrict__ C, int64_t ldc,
-                                     const float* __restrict__ bias) {
+                                     const float* __restrict__ bias, int sym) {
   const int64_t total = M * N;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.0f;
-    for (int z = 0; z < splits; z++) s += partial[(int64_t)z * total + i];
     const int64_t m = i / N, n = i - m * N;
+    // symmetric products computed only tiles at or above the diagonal
+    const int64_t src = (sym && m / BM > n / BN) ? n * N + m : i;
+    float s = 0.0f;
+    for (int z = 0; z < splits; z++) s += partial[(int64_t)z * total + src];
     if (bias) s += bias[n];
     C[m * ldc + n] = s;
   }
@@ -381,12 +401,12 @@ int gemm_pick_splits(int64_t M, int64_t N, int64_t Kd, int64_t* k_per_split) {
 }
 
 hipError_t splitk_reduce(const float* partial, int splits, int64_t M, int64_t N, float* C,
-                         int64_t ldc, const float* bias, hipStream_t s) {
+                         int64_t ldc, const float* bias, int sym, hipStream_t s) {
   const int64_t total = M * N;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  splitk_reduce_kernel<<<blocks, 256, 0, s>>>(partial, splits, M, N, C, ldc, bias);
+  splitk_reduce_kernel<<<blocks, 256, 0, s>>>(partial, splits, M, N, C, ldc, bias, sym);
   return hipGetLastError();
 }
 
@@ -402,33 +422,27 @@ hipError_t gemm(Elem t, bool a_trans, bool b_trans, const GemmArgs& g, hipStream
   dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN),
             (unsigned)(g.splits > 1 ? g.splits : 1));
   const int code = (a_trans ? 4 : 0) | (b_trans ? 2 : 0) | (vec ? 1 : 0);
-  if (t == Elem::F32) {
-    switch (code) {
-      case 0: gemm_f32<false, false, false><<<grid, 256, 0, s>>>(g); break;
-      case 1: gemm_f32<false, false, true><<<grid, 256, 0, s>>>(g); break;
-      case 2: gemm_f32<false, true, false><<<grid, 256, 0, s>>>(g); break;
-      case 3: gemm_f32<false, true, true><<<grid, 256, 0, s>>>(g); break;
-      case 4: gemm_f32<true, false, false><<<grid, 256, 0, s>>>(g); break;
-      case 5: gemm_f32<true, false, true><<<grid, 256, 0, s>>>(g); break;
-      case 6: gemm_f32<true, true, false><<<grid, 256, 0, s>>>(g); break;
-      case 7: gemm_f32<true, true, true><<<grid, 256, 0, s>>>(g); break;
-    }
-  } else {
-    switch (code) {
-      case 0: gemm_bf16<false, false, false><<<grid, 256, 0, s>>>(g); break;
-      case 1: gemm_bf16<false, false, true><<<grid, 256, 0, s>>>(g); break;
-      case 2: gemm_bf16<false, true, false><<<grid, 256, 0, s>>>(g); break;
-      case 3: gemm_bf16<false, true, true><<<grid, 256, 0, s>>>(g); break;
-      case 4: gemm_bf16<true, false, false><<<grid, 256, 0, s>>>(g); break;
-      case 5: gemm_bf16<true, false, true><<<grid, 256, 0, s>>>(g); break;
-      case 6: gemm_bf16<true, true, false><<<grid, 256, 0, s>>>(g); break;
-      case 7: gemm_bf16<true, true, true><<<grid, 256, 0, s>>>(g); break;
-    }
+#define PLNMF_GEMM_CASES(T)                                                             \
+  switch (code) {                                                                       \
+    case 0: gemm_kernel<T, false, false, false><<<grid, 256, 0, s>>>(g); break;         \
+    case 1: gemm_kernel<T, false, false, true><<<grid, 256, 0, s>>>(g); break;          \
+    case 2: gemm_kernel<T, false, true, false><<<grid, 256, 0, s>>>(g); break;          \
+    case 3: gemm_kernel<T, false, true, true><<<grid, 256, 0, s>>>(g); break;           \
+    case 4: gemm_kernel<T, true, false, false><<<grid, 256, 0, s>>>(g); break;          \
+    case 5: gemm_kernel<T, true, false, true><<<grid, 256, 0, s>>>(g); break;           \
+    case 6: gemm_kernel<T, true, true, false><<<grid, 256, 0, s>>>(g); break;           \
+    case 7: gemm_kernel<T, true, true, true><<<grid, 256, 0, s>>>(g); break;            \
   }
+  if (t == Elem::F32) {
+    PLNMF_GEMM_CASES(float)
+  } else {
+    PLNMF_GEMM_CASES(__bf16)
+  }
+#undef PLNMF_GEMM_CASES
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (g.splits > 1 && g.epi == EPI_STORE)
-    return splitk_reduce(g.partial, g.splits, g.M, g.N, g.C, g.ldc, g.bias, s);
+    return splitk_reduce(g.partial, g.splits, g.M, g.N, g.C, g.ldc, g.bias, g.sym, s);
   return hipSuccess;
 }
 

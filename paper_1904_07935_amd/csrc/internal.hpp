@@ -44,6 +44,7 @@ struct GemmArgs {
   int splits;      // split-K factor (EPI_STORE only); >1 needs `partial`
   int64_t k_per_split;
   float* partial;  // [splits][M][N]
+  int sym;         // 1: C is symmetric (M == N, op(A) = op(B)^T): upper tiles, mirrored
 };
 
 enum class Elem { F32, BF16 };
@@ -54,7 +55,7 @@ hipError_t gemm(Elem t, bool a_trans, bool b_trans, const GemmArgs& g, hipStream
 int gemm_pick_splits(int64_t M, int64_t N, int64_t Kd, int64_t* k_per_split);
 // C[M,N] (ldc) = sum_z partial[z] (+ bias[n])
 hipError_t splitk_reduce(const float* partial, int splits, int64_t M, int64_t N, float* C,
-                         int64_t ldc, const float* bias, hipStream_t s);
+                         int64_t ldc, const float* bias, int sym, hipStream_t s);
 
 // ------------------------------------------------------------------ SpMM ----
 // out[r, 0:K] = sum_j val[j] X[col[j], 0:K] over the rows of a CSR matrix.
@@ -126,7 +127,9 @@ struct HalsArgs {
 hipError_t hals_update(const HalsArgs& a, bool norm, int groups, hipStream_t s);
 int hals_w_groups(int64_t rows, int K, int device_cus);
 int hals_rows_per_group_h();
-int hals_w_max_coresident(int device_cus);
+int hals_w_max_coresident(int device_cus, int rows_per_group, int K);
+int hals_w_max_rows();
+size_t hals_smem_bytes(int rows_per_group, int K);
 
 // ----------------------------------------------------------------- MLP ----
 hipError_t mlp_init_params(float* master, int64_t n, int K, int hidden, uint64_t seed,

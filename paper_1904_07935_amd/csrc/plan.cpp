@@ -237,6 +237,7 @@ hipError_t plnmf::gram(nmf_plan_s* p, const float* X, int64_t rows, float* out) 
   g.epi = EPI_STORE;
   g.splits = gemm_pick_splits(g.M, g.N, g.Kd, &g.k_per_split);
   g.partial = p->partial;
+  g.sym = 1;
   return gemm(Elem::F32, true, false, g, p->stream);
 }
 
@@ -482,11 +483,12 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
     int v = atoi(env);
     if (v > 0) wg = std::min<int64_t>(v, (s.V + 31) / 32);
   }
-  const int maxco = hals_w_max_coresident(cus);
   int64_t rpg = (s.V + wg - 1) / wg;
-  if (rpg > 512) return bail(fail(NMF_E_UNSUPPORTED, "V=%lld needs more than %d persistent groups",
-                                  (long long)s.V, wg));
+  if (rpg > hals_w_max_rows())
+    return bail(fail(NMF_E_UNSUPPORTED, "V=%lld needs more than %d persistent groups",
+                     (long long)s.V, wg));
   wg = (int)((s.V + rpg - 1) / rpg);
+  const int maxco = hals_w_max_coresident(cus, (int)rpg, K);
   if (wg > maxco || wg > 1024)
     return bail(fail(NMF_E_UNSUPPORTED, "W update needs %d co-resident groups, device allows %d", wg,
                      maxco));
