@@ -1,0 +1,195 @@
+"""Throughput benchmark of the FAST-HALS sweep on one MI355X.
+
+Default workload: the bag-of-words stand-in for 20 Newsgroups (V = 26,000
+terms x D = 11,000 documents CSR, about 0.3% dense, Zipf(1.1) term
+popularity, tf-idf with unit-norm documents), K = 200, FP32 path.  A "step" is
+one full sweep of Alg. 1 (H half, then W half) with all inputs resident in HBM.
+
+Prints one JSON line:
+  value       sweeps per second (event-timed over --steps sweeps)
+  roofline    the dominant kernel's algorithmic work per launch divided by its
+              event-timed duration, against MI355X's published peak
+  cpu_baseline  the FP64 oracle (untiled Alg. 1, NumPy/SciPy) timed on this
+              host's cores on a bounded sample of the same workload
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HALS sweeps/s + % HBM/MFMA roofline; time-to-rel-objective 1e-4 vs plain FP32"
+PEAK = {"mfma_fp32_tflops": 157.3, "mfma_bf16_tflops": 2500.0, "hbm_gbs": 8000.0}
+COUNTERS = os.path.join(ROOT, "profiles", "counters.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--K", type=int, default=200)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--profile-sweeps", type=int, default=5)
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def step_work(step, V, D, K, nnz):
+    """Algorithmic work of one launch of a step: (amount, unit, bound, peak)."""
+    if step == "update_W":
+        return 2.0 * V * K * K, "flop", "mfma", PEAK["mfma_fp32_tflops"]
+    if step == "update_H":
+        return 2.0 * D * K * K, "flop", "mfma", PEAK["mfma_fp32_tflops"]
+    if step in ("gram_S", "gram_Q"):
+        rows = V if step == "gram_S" else D
+        return 2.0 * rows * K * K, "flop", "mfma", PEAK["mfma_fp32_tflops"]
+    # sparse products: CSR (index + value per nnz, row pointers), gathered factor
+    # read once, output written once (compulsory bytes)
+    rows_out, rows_x = (D, V) if step == "product_R" else (V, D)
+    b = 8.0 * nnz + 4.0 * (rows_out + 1) + 4.0 * K * (rows_out + rows_x)
+    return b, "byte", "hbm", PEAK["hbm_gbs"]
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ("hals.hip", "spmm.hip", "gemm.hip"):
+        with open(os.path.join(ROOT, "paper_1904_07935_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(step, workload):
+    """HBM bytes per launch from committed PMC counters, if they were taken on
+    the current kernel sources; else None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    try:
+        c = json.load(open(COUNTERS))
+    except ValueError:
+        return None
+    ent = c.get("entries", {}).get(f"{workload}:{step}")
+    if not ent or c.get("source_digest") != source_digest():
+        return None
+    return ent["hbm_bytes_per_launch"]
+
+
+def cpu_baseline(corpus, W0, H0, sweeps, min_seconds=10.0):
+    import numpy as np
+    import scipy.sparse as sp
+
+    from oracle import hals
+
+    A = sp.csr_matrix((corpus.A.val.astype(np.float64), corpus.A.col, corpus.A.rowptr),
+                      shape=(corpus.A.rows, corpus.A.cols))
+    W = hals.normalize_columns(W0)
+    H = H0.astype(np.float64)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    # at least `sweeps` sweeps and at least min_seconds of work (bounded sample)
+    t0 = time.perf_counter()
+    done = 0
+    while done < sweeps or (time.perf_counter() - t0 < min_seconds and done < 500):
+        W, H = hals.sweep(A, W, H, 1e-16)
+        done += 1
+    dt = time.perf_counter() - t0
+    sweeps = done
+    return {"value": sweeps / dt, "unit": "sweeps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{sweeps} full sweeps of the same workload (FP64 oracle, untiled Alg. 1, "
+                      f"NumPy/SciPy), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_1904_07935_amd.api import Matrix, Plan
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    K = args.K
+    corpus = datagen.c1()
+    V, D, nnz = corpus.A.rows, corpus.A.cols, corpus.A.nnz
+    W0, H0 = datagen.uniform_init_matched(V, D, K, datagen.mean_value(corpus.A), seed=1)
+    W = torch.tensor(W0, device=dev)
+    Ht = torch.tensor(np.ascontiguousarray(H0.T), device=dev)
+    plan = Plan(Matrix.from_csr(corpus.A, dev), W, Ht, eps=1e-16, precision=args.precision)
+    workload = f"c1_bow_{V}x{D}_k{K}_{args.precision}"
+
+    plan.sweep(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    plan.sweep(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+
+    # per-step event timing (separate pass; events on the plan's stream)
+    plan.profile(True)
+    plan.sweep(args.profile_sweeps)
+    plan.profile(False)
+    prof = plan.profile_read()
+    per_step_us = {k: 1000.0 * v[0] / max(v[1], 1) for k, v in prof.items()}
+    dominant = max(per_step_us, key=per_step_us.get)
+    amount, unit, bound, peak = step_work(dominant, V, D, K, nnz)
+    t = per_step_us[dominant] * 1e-6
+    if unit == "flop":
+        achieved, runit = amount / t / 1e12, "TFLOP/s"
+    else:
+        achieved, runit = amount / t / 1e9, "GB/s"
+    half, rel = plan.objective()
+    info = plan.info()
+    plan.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms, 2),
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16-products/f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "V": V, "D": D, "nnz": int(nnz), "K": K,
+                   "format": "csr", "precision": args.precision, "eps": 1e-16,
+                   "init": "U[0,1) W, H scaled to the data mean (seed 1)"},
+        "roofline": {"kernel": dominant, "bound": bound, "achieved": round(achieved, 3),
+                     "peak": peak, "unit": runit, "frac": round(achieved / peak, 5),
+                     "traffic": traffic_for(dominant, workload),
+                     "work_per_launch": amount, "work_unit": unit},
+        "per_step_us": {k: round(v, 2) for k, v in per_step_us.items()},
+        "w_groups": info["w_groups"],
+        "rel_objective": rel,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(corpus, W0, H0, args.cpu_sweeps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

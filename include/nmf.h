@@ -127,6 +127,23 @@ int nmf_intermediates(nmf_plan plan, const float** P, const float** Q, const flo
                       const float** S);
 
 int nmf_plan_info(nmf_plan plan, nmf_info* info);
+
+/* Per-step timing with HIP events recorded on the plan's stream around each
+ * step of nmf_sweep / nmf_half.  Steps: */
+#define NMF_STEP_GRAM_S 0    /* S = W^T W                       (H half)       */
+#define NMF_STEP_PRODUCT_R 1 /* R = A^T W, incl. BF16 operand cast            */
+#define NMF_STEP_UPDATE_H 2  /* tiled H update: one kernel launch             */
+#define NMF_STEP_PRODUCT_P 3 /* P = A H^T, incl. BF16 operand cast   (W half) */
+#define NMF_STEP_GRAM_Q 4    /* Q = H H^T                                     */
+#define NMF_STEP_UPDATE_W 5  /* persistent tiled W update: one kernel launch  */
+#define NMF_STEP_COUNT 6
+/* enable != 0 starts recording (events are created by the library and freed
+ * by nmf_profile_read or nmf_destroy); enable == 0 stops.                    */
+int nmf_profile(nmf_plan plan, int enable);
+/* Sum of event-timed milliseconds and number of recorded launches per step
+ * (host arrays of NMF_STEP_COUNT) since the last read; synchronises the
+ * stream and resets the record.                                              */
+int nmf_profile_read(nmf_plan plan, double* ms_total, int64_t* launches);
 int nmf_set_stream(nmf_plan plan, void* stream);
 int nmf_destroy(nmf_plan plan);
 const char* nmf_last_error(void);

@@ -20,6 +20,7 @@ NMF_FP32, NMF_BF16_PRODUCTS = 0, 1
 NMF_HALF_H, NMF_HALF_W = 0, 1
 NMF_FOLDIN_GIVEN, NMF_FOLDIN_WTA, NMF_FOLDIN_MLP = 0, 1, 2
 NMF_MAX_K = 512
+STEP_NAMES = ["gram_S", "product_R", "update_H", "product_P", "gram_Q", "update_W"]
 
 
 class NativeLibraryMissing(RuntimeError):
@@ -61,6 +62,8 @@ SIGNATURES = {
     "nmf_plan_info": [_P, POINTER(nmf_info)],
     "nmf_set_stream": [_P, _P],
     "nmf_destroy": [_P],
+    "nmf_profile": [_P, c_int],
+    "nmf_profile_read": [_P, POINTER(c_double), POINTER(c_int64)],
     "nmf_foldin_workspace_bytes": [_P, POINTER(nmf_matrix), c_int, POINTER(c_size_t)],
     "nmf_foldin": [_P, POINTER(nmf_matrix), _P, c_int, _P, c_int, c_int, POINTER(c_double), _P,
                    c_size_t],

@@ -130,6 +130,18 @@ class Plan:
             out[name] = _view(self.ws, p.value, shp[0] * shp[1], torch.float32).view(*shp)
         return out
 
+    def profile(self, enable=True):
+        """Record HIP events around every step (see ``profile_read``)."""
+        L.call("nmf_profile", self.h, 1 if enable else 0)
+
+    def profile_read(self):
+        """{step: (total ms, launches)} since the last read; synchronises."""
+        n = len(L.STEP_NAMES)
+        ms = (c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        L.call("nmf_profile_read", self.h, ms, cnt)
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(L.STEP_NAMES)}
+
     def info(self):
         i = L.nmf_info()
         L.call("nmf_plan_info", self.h, byref(i))

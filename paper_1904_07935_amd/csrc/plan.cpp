@@ -324,9 +324,49 @@ unsigned next_epoch(nmf_plan_s* p) {
   return e;
 }
 
+// event pair around one step on the plan's stream (profiling only)
+hipEvent_t prof_begin(nmf_plan_s* p) {
+  if (!p->profiling) return nullptr;
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventRecord(e, p->stream) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void prof_end(nmf_plan_s* p, int step, hipEvent_t e0) {
+  if (!e0) return;
+  hipEvent_t e1 = nullptr;
+  if (hipEventCreate(&e1) != hipSuccess || hipEventRecord(e1, p->stream) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return;
+  }
+  p->prof[step].push_back({e0, e1});
+}
+
+#define TIMED(p, step, expr)                 \
+  do {                                       \
+    hipEvent_t ev0_ = prof_begin(p);         \
+    HIPCHECK(p, expr);                       \
+    prof_end(p, step, ev0_);                 \
+  } while (0)
+
+void prof_clear(nmf_plan_s* p) {
+  for (auto& v : p->prof) {
+    for (auto& e : v) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    v.clear();
+  }
+}
+
 int half_h(nmf_plan_s* p) {
-  HIPCHECK(p, gram(p, p->W, p->V, p->S));
-  HIPCHECK(p, product_R(p));
+  TIMED(p, NMF_STEP_GRAM_S, gram(p, p->W, p->V, p->S));
+  TIMED(p, NMF_STEP_PRODUCT_R, product_R(p));
   HalsArgs a{};
   a.X = p->Ht;
   a.Bterm = p->R;
@@ -336,14 +376,14 @@ int half_h(nmf_plan_s* p) {
   a.eps = p->eps;
   a.diag_one = 1;
   a.status = p->status;
-  HIPCHECK(p, hals_update(a, false, 0, p->stream));
+  TIMED(p, NMF_STEP_UPDATE_H, hals_update(a, false, 0, p->stream));
   p->pq_valid = false;
   return NMF_OK;
 }
 
 int half_w(nmf_plan_s* p) {
-  HIPCHECK(p, product_P(p, false, p->P));
-  HIPCHECK(p, gram(p, p->Ht, p->D, p->Q));
+  TIMED(p, NMF_STEP_PRODUCT_P, product_P(p, false, p->P));
+  TIMED(p, NMF_STEP_GRAM_Q, gram(p, p->Ht, p->D, p->Q));
   HalsArgs a{};
   a.X = p->W;
   a.Bterm = p->P;
@@ -356,7 +396,7 @@ int half_w(nmf_plan_s* p) {
   a.slots = p->slots;
   a.epoch = next_epoch(p);
   a.status = p->status;
-  HIPCHECK(p, hals_update(a, true, p->w_groups, p->stream));
+  TIMED(p, NMF_STEP_UPDATE_W, hals_update(a, true, p->w_groups, p->stream));
   p->pq_valid = p->prec == NMF_FP32;
   return NMF_OK;
 }
@@ -648,7 +688,31 @@ int nmf_set_stream(nmf_plan p, void* stream) {
   return NMF_OK;
 }
 
+int nmf_profile(nmf_plan p, int enable) {
+  if (!p) return fail(NMF_E_ARG, "plan is NULL");
+  p->profiling = enable != 0;
+  return NMF_OK;
+}
+
+int nmf_profile_read(nmf_plan p, double* ms_total, int64_t* launches) {
+  if (!p || !ms_total || !launches) return fail(NMF_E_ARG, "NULL argument");
+  HIPCHECK(p, hipStreamSynchronize(p->stream));
+  for (int s = 0; s < NMF_STEP_COUNT; s++) {
+    double tot = 0.0;
+    for (auto& e : p->prof[s]) {
+      float ms = 0.0f;
+      HIPCHECK(p, hipEventElapsedTime(&ms, e.first, e.second));
+      tot += ms;
+    }
+    ms_total[s] = tot;
+    launches[s] = (int64_t)p->prof[s].size();
+  }
+  prof_clear(p);
+  return NMF_OK;
+}
+
 int nmf_destroy(nmf_plan p) {
+  if (p) prof_clear(p);
   delete p;
   return NMF_OK;
 }

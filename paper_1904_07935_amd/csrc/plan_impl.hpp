@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/nmf.h"
 #include "internal.hpp"
@@ -88,6 +90,8 @@ struct nmf_plan_s {
   int64_t sweeps_done = 0;
   bool pq_valid = false;
   int poisoned = 0;
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof[NMF_STEP_COUNT];
 };
 
 namespace plnmf {

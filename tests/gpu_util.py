@@ -53,3 +53,16 @@ def small_bow(V=3000, D=1200, seed=2):
 def sparse_init(c, K, seed=1):
     """Scale-matched U[0,1) init for a bag-of-words corpus (see datagen)."""
     return datagen.uniform_init_matched(c.A.rows, c.A.cols, K, datagen.mean_value(c.A), seed)
+
+
+def bf16_round(x):
+    """Round float32 values to the nearest bfloat16 (ties to even), as float64."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def rows_csr_to_oracle(csr):
+    """A doc-major CSR (rows = documents) as the oracle's V x D' matrix."""
+    m = sp.csr_matrix((csr.val.astype(np.float64), csr.col, csr.rowptr), shape=(csr.rows, csr.cols))
+    return m.T.tocsr()
