@@ -27,8 +27,9 @@ struct FoldWs {
   double* red;
   double* scal;   // [0] a2 [1] wp [2] sq [3] half [4] rel
   double* trace;  // [kTraceChunk]
-  int32_t* chunk_row;
-  int32_t* fix_rows;
+  int4* items;
+  int32_t* item_slot;
+  int32_t* fix;
   float* carry;
   int32_t* counter;
   float* xn;      // MLP input [D',K]
@@ -37,8 +38,7 @@ struct FoldWs {
   void* mlp_ws;
   size_t mlp_ws_bytes;
   size_t off;
-  int chunk;
-  int64_t nchunks;
+  int L;
 };
 
 FoldWs fold_layout(void* base, int64_t Dn, int64_t V, int K, const nmf_matrix* AnewT, int hidden) {
@@ -62,11 +62,12 @@ FoldWs fold_layout(void* base, int64_t Dn, int64_t V, int K, const nmf_matrix* A
   f.scal = c.take<double>(8);
   f.trace = c.take<double>(kTraceChunk);
   if (AnewT->format == NMF_CSR) {
-    f.chunk = spmm_chunk_for(AnewT->nnz);
-    f.nchunks = (AnewT->nnz + f.chunk - 1) / f.chunk;
-    f.chunk_row = c.take<int32_t>((size_t)std::max<int64_t>(f.nchunks, 1));
-    f.fix_rows = c.take<int32_t>((size_t)Dn);
-    f.carry = c.take<float>((size_t)std::max<int64_t>(f.nchunks * 2 * K, 1));
+    f.L = spmm_item_nnz(AnewT->nnz);
+    const SpmmSizes z = spmm_sizes(Dn, AnewT->nnz, f.L);
+    f.items = c.take<int4>((size_t)z.items);
+    f.item_slot = c.take<int32_t>((size_t)z.items);
+    f.fix = c.take<int32_t>((size_t)(3 * z.fix));
+    f.carry = c.take<float>((size_t)(z.seg * K));
     f.counter = c.take<int32_t>(4);
   }
   if (hidden > 0) {
@@ -177,13 +178,15 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
     SpmmPlan sp{};
     sp.rows = Dn;
     sp.nnz = AnewT->nnz;
-    sp.chunk = f.chunk;
-    sp.nchunks = f.nchunks;
+    sp.L = f.L;
     sp.rowptr = AnewT->rowptr;
     sp.col = AnewT->colidx;
     sp.val = AnewT->values;
+    sp.items = f.items;
+    sp.item_slot = f.item_slot;
+    sp.fix = f.fix;
     sp.carry = f.carry;
-    FCHECK(spmm_build(&sp, K, f.chunk_row, f.fix_rows, f.counter, s));
+    FCHECK(spmm_build(&sp, s));
     FCHECK(spmm(sp, Elem::F32, p->W, K, f.R, s));
     const int nb = reduce_blocks(AnewT->nnz);
     FCHECK(sumsq_f64(AnewT->values, AnewT->nnz, f.red, nb, s));

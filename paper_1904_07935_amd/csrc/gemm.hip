@@ -298,6 +298,36 @@ struct Mfma<__bf16> {
   }
 };
 
+// Main loop: two register stages and two LDS buffers.  The global load of
+// K-step k + 2 is issued before computing step k and stored to LDS after
+// computing step k + 1, so each load has two compute steps to arrive.
+template <typename T, typename St, typename TA, typename TB>
+__device__ __forceinline__ void pipeline(TA As, TB Bs, const T* __restrict__ A,
+                                         const T* __restrict__ B, int64_t lda, int64_t ldb,
+                                         int64_t M, int64_t N, int64_t m0, int64_t n0, int64_t kb,
+                                         int64_t ke, int nk, int tid, floatx16 (&acc)[2][2], int wm,
+                                         int wn, int lane) {
+  constexpr int BK = Mfma<T>::BK;
+  St s0, s1;
+  if (nk > 0) s0.load(A, B, lda, ldb, M, N, m0, n0, kb, ke, tid);
+  if (nk > 1) s1.load(A, B, lda, ldb, M, N, m0, n0, kb + BK, ke, tid);
+  if (nk > 0) {
+    s0.store(As[0], Bs[0], tid);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; kt += 2) {
+    if (kt + 2 < nk) s0.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 2) * BK, ke, tid);
+    Mfma<T>::step(As[0], Bs[0], acc, wm, wn, lane);
+    if (kt + 1 < nk) s1.store(As[1], Bs[1], tid);
+    __syncthreads();
+    if (kt + 1 >= nk) break;
+    if (kt + 3 < nk) s1.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 3) * BK, ke, tid);
+    Mfma<T>::step(As[1], Bs[1], acc, wm, wn, lane);
+    if (kt + 2 < nk) s0.store(As[0], Bs[0], tid);
+    __syncthreads();
+  }
+}
+
 template <typename T, bool AT, bool BT, bool VEC>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   constexpr int BK = Mfma<T>::BK;
@@ -331,35 +361,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   if constexpr (std::is_same<T, float>::value) {
     __shared__ float As[2][BK][St::LDS_A];
     __shared__ float Bs[2][BK][St::LDS_B];
-    St st;
-    if (nk > 0) {
-      st.load(A, B, lda, ldb, M, N, m0, n0, kb, ke, tid);
-      st.store(As[0], Bs[0], tid);
-      __syncthreads();
-    }
-    for (int kt = 0; kt < nk; kt++) {
-      const int buf = kt & 1;
-      if (kt + 1 < nk) st.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 1) * BK, ke, tid);
-      Mfma<T>::step(As[buf], Bs[buf], acc, wm, wn, lane);
-      if (kt + 1 < nk) st.store(As[buf ^ 1], Bs[buf ^ 1], tid);
-      __syncthreads();
-    }
+    pipeline<T, St>(As, Bs, A, B, lda, ldb, M, N, m0, n0, kb, ke, nk, tid, acc, wm, wn, lane);
   } else {
     __shared__ __bf16 As[2][BM][St::LDS_K];
     __shared__ __bf16 Bs[2][BN][St::LDS_K];
-    St st;
-    if (nk > 0) {
-      st.load(A, B, lda, ldb, M, N, m0, n0, kb, ke, tid);
-      st.store(As[0], Bs[0], tid);
-      __syncthreads();
-    }
-    for (int kt = 0; kt < nk; kt++) {
-      const int buf = kt & 1;
-      if (kt + 1 < nk) st.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 1) * BK, ke, tid);
-      Mfma<T>::step(As[buf], Bs[buf], acc, wm, wn, lane);
-      if (kt + 1 < nk) st.store(As[buf ^ 1], Bs[buf ^ 1], tid);
-      __syncthreads();
-    }
+    pipeline<T, St>(As, Bs, A, B, lda, ldb, M, N, m0, n0, kb, ke, nk, tid, acc, wm, wn, lane);
   }
   const bool split = splits > 1;
   float* out = split ? g.partial + (int64_t)blockIdx.z * M * N : g.C;

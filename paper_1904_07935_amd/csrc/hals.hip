@@ -74,17 +74,22 @@ __device__ __forceinline__ unsigned long long pack_slot(unsigned tag, float v) {
   return ((unsigned long long)tag << 32) | (unsigned long long)__float_as_uint(v);
 }
 
+// The slot array is replicated kSlotReplicas times (kSlotStride apart): every
+// group writes its partial into all replicas and polls only replica g %
+// kSlotReplicas, so the polling traffic of all groups does not converge on the
+// same few cache lines.  Called by lanes 0..kSlotReplicas-1 of one wave.
 __device__ __forceinline__ void publish(unsigned long long* slots, int groups, int g, unsigned tag,
-                                        int par, float mine) {
-  __hip_atomic_store(slots + (int64_t)par * groups + g, pack_slot(tag, mine), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
+                                        int par, float mine, int replica) {
+  __hip_atomic_store(slots + (int64_t)replica * kSlotStride + (int64_t)par * groups + g,
+                     pack_slot(tag, mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Chip-wide fixed-order sum of the published partials (wave 0, all lanes).
-__device__ float collect_sum(const unsigned long long* slots, int groups, unsigned tag, int par,
-                             int32_t* status) {
+__device__ float collect_sum(const unsigned long long* slots, int groups, int g, unsigned tag,
+                             int par, int32_t* status) {
   const int lane = threadIdx.x & 63;
-  const unsigned long long* base = slots + (int64_t)par * groups;
+  const unsigned long long* base =
+      slots + (int64_t)(g % kSlotReplicas) * kSlotStride + (int64_t)par * groups;
   constexpr int MAXS = 16;  // groups <= 1024
   unsigned long long v[MAXS];
   int spins = 0;
@@ -296,7 +301,8 @@ __global__ __launch_bounds__(256) void hals_kernel(HalsArgs a) {
         __syncthreads();
         const unsigned tag = (a.epoch << 10) | (unsigned)(a0 + t);
         const int par = (a0 + t) & 1;
-        if (tid == 0) publish(a.slots, groups, g, tag, par, sm.red[0] + sm.red[1] + sm.red[2] + sm.red[3]);
+        if (tid < kSlotReplicas)
+          publish(a.slots, groups, g, tag, par, sm.red[0] + sm.red[1] + sm.red[2] + sm.red[3], tid);
         // off the critical path: the previous column's contribution to columns > t
         if (t > 0) {
 #pragma unroll
@@ -307,7 +313,7 @@ __global__ __launch_bounds__(256) void hals_kernel(HalsArgs a) {
           }
         }
         if (w == 0) {
-          const float tot = collect_sum(a.slots, groups, tag, par, a.status);
+          const float tot = collect_sum(a.slots, groups, g, tag, par, a.status);
           if (lane == 0) sm.red[4] = tot;
         }
         __syncthreads();

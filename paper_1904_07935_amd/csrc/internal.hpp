@@ -15,6 +15,9 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxK = 512;
 constexpr int kTile = 32;          // tile width T of the column-update kernels
 constexpr int kSpinLimit = 1 << 21; // bounded waits: a few seconds of polling at most
+constexpr int kSlotReplicas = 8;    // copies of the column-norm exchange slots
+constexpr int kSlotStride = 2 * 1024 + 16;  // u64 elements between replicas
+constexpr int kSlotWords = kSlotReplicas * kSlotStride;
 
 // ------------------------------------------------------------------ GEMM ----
 // C[M,N] = sum_k A(m,k) B(k,n) with FP32 accumulation on the matrix cores.
@@ -59,22 +62,31 @@ hipError_t splitk_reduce(const float* partial, int splits, int64_t M, int64_t N,
 
 // ------------------------------------------------------------------ SpMM ----
 // out[r, 0:K] = sum_j val[j] X[col[j], 0:K] over the rows of a CSR matrix.
-// nnz is cut into chunks of `chunk` entries; rows crossing a chunk boundary are
-// finished by a fixed-order fixup pass over `carry` [nchunks][2][K].
+// Work items (one wave each), planned on the host by spmm_build: runs of short
+// rows holding about L nonzeros, or one segment of L nonzeros of a long row;
+// segments leave partial rows in `carry` that a fixed-order pass adds up.
 struct SpmmPlan {
   int64_t rows, nnz;
-  int chunk;
-  int64_t nchunks;
   const int32_t* rowptr;
   const int32_t* col;
   const void* val;        // float or bf16 (elem)
-  const int32_t* chunk_row;  // [nchunks] row holding the chunk's first entry
-  const int32_t* fix_rows;   // rows that are split across chunks or empty
+  int L;                  // target nonzeros per work item
+  int4* items;            // [n_items] (first row, end row, first nz, end nz)
+  int32_t* item_slot;     // [n_items] carry row of a segment, or -1
+  int64_t n_items;
+  int32_t* fix;           // [n_fix][3] (row, first segment, segments)
   int64_t n_fix;
-  float* carry;            // [nchunks][2][K]
+  float* carry;           // [n_seg][K]
+  int64_t n_seg;
 };
-hipError_t spmm_build(SpmmPlan* p, int K, int32_t* chunk_row_buf, int32_t* fix_rows_buf,
-                      int32_t* counter, hipStream_t s);
+struct SpmmSizes {
+  int64_t items, fix, seg;  // upper bounds for any row structure
+};
+int spmm_item_nnz(int64_t nnz);
+SpmmSizes spmm_sizes(int64_t rows, int64_t nnz, int L);
+// Copies the row pointers to the host, plans the items, uploads them
+// (synchronises the stream).  Device buffers must be sized by spmm_sizes.
+hipError_t spmm_build(SpmmPlan* p, hipStream_t s);
 hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hipStream_t s);
 
 // CSR transpose (rows x cols -> cols x rows), deterministic, rows sorted.

@@ -35,12 +35,6 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-int spmm_chunk_for(int64_t nnz) {
-  int64_t c = 128;
-  while (nnz / c > 32768) c *= 2;  // bounds the carry buffer
-  return (int)c;
-}
-
 }  // namespace plnmf
 
 namespace {
@@ -99,7 +93,7 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
   const int red_n = (int)std::max<int64_t>(std::max<int64_t>(resid_tiles, 1024), 1);
   double* red = c.take<double>((size_t)red_n);
   double* scal = c.take<double>(16);
-  unsigned long long* slots = c.take<unsigned long long>(2 * 1024);
+  unsigned long long* slots = c.take<unsigned long long>(kSlotWords);
   int32_t* status = c.take<int32_t>(16);
   double* colsq = c.take<double>((size_t)1024 * K);
   if (p) {
@@ -116,14 +110,16 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
     int32_t* t_rowptr = c.take<int32_t>((size_t)(D + 1));
     int32_t* t_col = c.take<int32_t>((size_t)std::max<int64_t>(nnz, 1));
     float* t_val = c.take<float>((size_t)std::max<int64_t>(nnz, 1));
-    const int chunk = spmm_chunk_for(nnz);
-    const int64_t nch = (nnz + chunk - 1) / chunk;
-    int32_t* chA = c.take<int32_t>((size_t)std::max<int64_t>(nch, 1));
-    int32_t* fixA = c.take<int32_t>((size_t)V);
-    float* carryA = c.take<float>((size_t)std::max<int64_t>(nch * 2 * K, 1));
-    int32_t* chT = c.take<int32_t>((size_t)std::max<int64_t>(nch, 1));
-    int32_t* fixT = c.take<int32_t>((size_t)D);
-    float* carryT = c.take<float>((size_t)std::max<int64_t>(nch * 2 * K, 1));
+    const int L = spmm_item_nnz(nnz);
+    const SpmmSizes zA = spmm_sizes(V, nnz, L), zT = spmm_sizes(D, nnz, L);
+    int4* itA = c.take<int4>((size_t)zA.items);
+    int32_t* slA = c.take<int32_t>((size_t)zA.items);
+    int32_t* fixA = c.take<int32_t>((size_t)(3 * zA.fix));
+    float* carryA = c.take<float>((size_t)(zA.seg * K));
+    int4* itT = c.take<int4>((size_t)zT.items);
+    int32_t* slT = c.take<int32_t>((size_t)zT.items);
+    int32_t* fixT = c.take<int32_t>((size_t)(3 * zT.fix));
+    float* carryT = c.take<float>((size_t)(zT.seg * K));
     __bf16 *avb = nullptr, *tvb = nullptr, *xb = nullptr;
     float* P2 = nullptr;
     if (s.prec == NMF_BF16_PRODUCTS) {
@@ -136,13 +132,14 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
       p->t_rowptr = t_rowptr;
       p->t_col = t_col;
       p->t_val = t_val;
-      p->sp_A.chunk = p->sp_At.chunk = chunk;
-      p->sp_A.nchunks = p->sp_At.nchunks = nch;
-      p->sp_A.chunk_row = chA;
-      p->sp_A.fix_rows = fixA;
+      p->sp_A.L = p->sp_At.L = L;
+      p->sp_A.items = itA;
+      p->sp_A.item_slot = slA;
+      p->sp_A.fix = fixA;
       p->sp_A.carry = carryA;
-      p->sp_At.chunk_row = chT;
-      p->sp_At.fix_rows = fixT;
+      p->sp_At.items = itT;
+      p->sp_At.item_slot = slT;
+      p->sp_At.fix = fixT;
       p->sp_At.carry = carryT;
       p->a_val_bf = avb;
       p->t_val_bf = tvb;
@@ -536,7 +533,7 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
   p->w_rows_per_group = (int)rpg;
 
   INITCHECK(hipMemsetAsync(p->status, 0, 16 * sizeof(int32_t), st));
-  INITCHECK(hipMemsetAsync(p->slots, 0, 2 * 1024 * sizeof(unsigned long long), st));
+  INITCHECK(hipMemsetAsync(p->slots, 0, kSlotWords * sizeof(unsigned long long), st));
   // input checks: W, Ht finite and non-negative; A structure and values
   INITCHECK(check_finite_nonneg(W, s.V * K, p->status, 1, st));
   INITCHECK(check_finite_nonneg(Ht, s.D * K, p->status, 2, st));
@@ -572,10 +569,8 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
     p->sp_At.rowptr = p->t_rowptr;
     p->sp_At.col = p->t_col;
     p->sp_At.val = p->t_val;
-    INITCHECK(spmm_build(&p->sp_A, K, (int32_t*)p->sp_A.chunk_row, (int32_t*)p->sp_A.fix_rows,
-                         p->status + 8, st));
-    INITCHECK(spmm_build(&p->sp_At, K, (int32_t*)p->sp_At.chunk_row, (int32_t*)p->sp_At.fix_rows,
-                         p->status + 8, st));
+    INITCHECK(spmm_build(&p->sp_A, st));
+    INITCHECK(spmm_build(&p->sp_At, st));
     if (precision == NMF_BF16_PRODUCTS) {
       p->sp_A_f32 = p->sp_A;
       INITCHECK(cast_bf16(A->values, p->a_val_bf, s.nnz, st));

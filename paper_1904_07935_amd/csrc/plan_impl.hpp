@@ -41,7 +41,6 @@ struct Carver {
   }
 };
 
-int spmm_chunk_for(int64_t nnz);
 int device_check(int* dev, int* cus);
 int check_matrix(const nmf_matrix* A);
 

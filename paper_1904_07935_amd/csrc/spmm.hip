@@ -3,13 +3,19 @@
 // Ht); the sparse-matrix/dense-matrix products of Alg. 1 (R and P statements)
 // and of the GPU implementation in Sec. 4.2.
 //
-// Design: the nnz range is cut into equal chunks, one wave per chunk, so the
-// Zipf-skewed row lengths of a term-by-document matrix do not unbalance the
-// grid.  Each nnz gathers one K-contiguous factor row with 16-byte (FP32) or
-// 8-byte (BF16) lane loads; several nnz are in flight per wave.  Rows that cross
-// a chunk boundary leave per-chunk partials in a carry buffer that a second,
-// fixed-order pass adds up, and that pass also zeroes empty rows: no atomics,
-// bitwise-reproducible results.
+// Design: one wave per work item.  Items are planned once on the host from the
+// row pointers: consecutive short rows are grouped until an item holds about
+// L nonzeros (empty rows included, written as zeros), and a row longer than L
+// -- the Zipf-skewed head of a term-by-document matrix -- is cut into segments
+// of L.  So the grid stays balanced whatever the row-length skew.  Each nonzero
+// gathers one K-contiguous factor row with 16-byte (FP32) or 8-byte (BF16)
+// lane loads, several nonzeros in flight per wave.  Segments of long rows
+// leave partial rows that a second pass adds up in segment order; nothing
+// else needs a second pass, and no atomics are used: results are
+// bitwise-reproducible.
+#include <algorithm>
+#include <vector>
+
 #include "internal.hpp"
 
 namespace plnmf {
@@ -19,13 +25,12 @@ struct SpmmKArgs {
   const int32_t* rowptr;
   const int32_t* col;
   const void* val;
-  const int32_t* chunk_row;
+  const int4* items;
+  const int32_t* slot;
   const void* X;
   float* out;
   float* carry;
-  int64_t nnz;
-  int64_t nchunks;
-  int chunk;
+  int64_t n_items;
   int K;
 };
 
@@ -57,27 +62,24 @@ __device__ __forceinline__ floatx4 ld_x4(const TX* row, int c, int K) {
 }
 
 template <int VPL, int LPN, typename TV, typename TX, bool VEC>
-__global__ __launch_bounds__(256) void spmm_chunks(SpmmKArgs a) {
-  constexpr int NPAR = 64 / LPN;
+__global__ __launch_bounds__(256) void spmm_items(SpmmKArgs a) {
+  constexpr int NPAR = 64 / LPN;  // nonzeros processed side by side per wave
   constexpr int UNR = 4;
   const int lane = threadIdx.x & 63;
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= a.nchunks) return;
+  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (it >= a.n_items) return;
   const int grp = lane / LPN, q = lane % LPN;
   const int K = a.K;
   const TX* X = (const TX*)a.X;
-  const int64_t j0 = c * a.chunk;
-  const int64_t j1 = j0 + a.chunk < a.nnz ? j0 + a.chunk : a.nnz;
-  int64_t r = a.chunk_row[c];
-  int64_t j = j0;
-  while (j < j1) {
-    const int64_t rs = a.rowptr[r], re = a.rowptr[r + 1];
-    const int64_t se = re < j1 ? re : j1;
+  const int4 item = a.items[it];
+  const int slot = a.slot[it];
+  for (int r = item.x; r < item.y; r++) {
+    const int64_t rs = max(a.rowptr[r], item.z), re = min(a.rowptr[r + 1], item.w);
     floatx4 acc[VPL];
 #pragma unroll
     for (int v = 0; v < VPL; v++) acc[v] = floatx4{0, 0, 0, 0};
-    int64_t jj = j + grp;
-    for (; jj + (UNR - 1) * NPAR < se; jj += UNR * NPAR) {
+    int64_t jj = rs + grp;
+    for (; jj + (UNR - 1) * NPAR < re; jj += UNR * NPAR) {
       int32_t cc[UNR];
       float vv[UNR];
 #pragma unroll
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(256) void spmm_chunks(SpmmKArgs a) {
 #pragma unroll
         for (int v = 0; v < VPL; v++) acc[v] += vv[u] * x[u][v];
     }
-    for (; jj < se; jj += NPAR) {
+    for (; jj < re; jj += NPAR) {
       const int32_t cc = a.col[jj];
       const float vv = ld_val<TV>(a.val, jj);
 #pragma unroll
@@ -108,10 +110,7 @@ __global__ __launch_bounds__(256) void spmm_chunks(SpmmKArgs a) {
       for (int v = 0; v < VPL; v++)
 #pragma unroll
         for (int e = 0; e < 4; e++) acc[v][e] += __shfl_xor(acc[v][e], off);
-    float* dst;
-    if (rs >= j0 && re <= j1) dst = a.out + r * K;                     // whole row here
-    else if (rs < j0) dst = a.carry + (c * 2 + 0) * K;                 // head partial
-    else dst = a.carry + (c * 2 + 1) * K;                              // tail partial
+    float* dst = slot >= 0 ? a.carry + (int64_t)slot * K : a.out + (int64_t)r * K;
     if (grp == 0) {
 #pragma unroll
       for (int v = 0; v < VPL; v++) {
@@ -121,69 +120,30 @@ __global__ __launch_bounds__(256) void spmm_chunks(SpmmKArgs a) {
           if (cb + e < K) dst[cb + e] = acc[v][e];
       }
     }
-    j = se;
-    if (j < j1) {
-      r++;
-      while (a.rowptr[r + 1] <= j) r++;  // skip empty rows (zeroed by the fixup)
-    }
   }
 }
 
-// One wave per listed row: zero an empty row, or add the chunk partials of a
-// row split across chunks in chunk order.
-__global__ __launch_bounds__(256) void spmm_fixup(const int32_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ fix_rows,
-                                                  int64_t n_fix, const float* __restrict__ carry,
-                                                  float* __restrict__ out, int K, int chunk) {
+// One wave per long row: add its segments' partial rows in segment order.
+__global__ __launch_bounds__(256) void spmm_fixup(const int32_t* __restrict__ fix, int64_t n_fix,
+                                                  const float* __restrict__ carry,
+                                                  float* __restrict__ out, int K) {
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n_fix) return;
   const int lane = threadIdx.x & 63;
-  const int64_t r = fix_rows[i];
-  const int64_t rs = rowptr[r], re = rowptr[r + 1];
-  if (rs == re) {
-    for (int k = lane; k < K; k += 64) out[r * K + k] = 0.0f;
-    return;
-  }
-  const int64_t c0 = rs / chunk, c1 = (re - 1) / chunk;
+  const int64_t r = fix[3 * i], first = fix[3 * i + 1], cnt = fix[3 * i + 2];
   for (int k = lane; k < K; k += 64) {
-    float s = carry[(c0 * 2 + 1) * K + k];
-    for (int64_t c = c0 + 1; c <= c1; c++) s += carry[(c * 2 + 0) * K + k];
+    float s = 0.0f;
+    for (int64_t g = 0; g < cnt; g++) s += carry[(first + g) * K + k];
     out[r * K + k] = s;
-  }
-}
-
-__global__ void spmm_chunk_rows(const int32_t* __restrict__ rowptr, int64_t rows, int64_t nchunks,
-                                int chunk, int32_t* __restrict__ chunk_row) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nchunks) return;
-  const int64_t j = c * chunk;
-  // first row whose end exceeds j
-  int64_t lo = 0, hi = rows - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (rowptr[mid + 1] > j) hi = mid; else lo = mid + 1;
-  }
-  chunk_row[c] = (int32_t)lo;
-}
-
-__global__ void spmm_find_fix(const int32_t* __restrict__ rowptr, int64_t rows, int chunk,
-                              int32_t* __restrict__ fix_rows, int32_t* __restrict__ counter) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  const int64_t rs = rowptr[r], re = rowptr[r + 1];
-  const bool need = (rs == re) || (rs / chunk != (re - 1) / chunk);
-  if (need) {
-    const int slot = atomicAdd(counter, 1);
-    fix_rows[slot] = (int32_t)r;
   }
 }
 
 template <int VPL, int LPN, typename TV, typename TX>
 hipError_t launch_t(const SpmmKArgs& a, bool vec, hipStream_t s) {
-  const unsigned blocks = (unsigned)((a.nchunks + 3) / 4);
+  const unsigned blocks = (unsigned)((a.n_items + 3) / 4);
   if (blocks == 0) return hipSuccess;
-  if (vec) spmm_chunks<VPL, LPN, TV, TX, true><<<blocks, 256, 0, s>>>(a);
-  else spmm_chunks<VPL, LPN, TV, TX, false><<<blocks, 256, 0, s>>>(a);
+  if (vec) spmm_items<VPL, LPN, TV, TX, true><<<blocks, 256, 0, s>>>(a);
+  else spmm_items<VPL, LPN, TV, TX, false><<<blocks, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -200,30 +160,78 @@ hipError_t launch_k(const SpmmKArgs& a, bool vec, hipStream_t s) {
   return launch_t<2, 64, TV, TX>(a, vec, s);  // K <= 512
 }
 
+constexpr int kMaxRowsPerItem = 256;
+
 }  // namespace
 
-hipError_t spmm_build(SpmmPlan* p, int K, int32_t* chunk_row_buf, int32_t* fix_rows_buf,
-                      int32_t* counter, hipStream_t s) {
-  p->chunk_row = chunk_row_buf;
-  p->fix_rows = fix_rows_buf;
-  if (p->nchunks > 0) {
-    spmm_chunk_rows<<<(unsigned)((p->nchunks + 255) / 256), 256, 0, s>>>(
-        p->rowptr, p->rows, p->nchunks, p->chunk, chunk_row_buf);
-  }
-  hipError_t e = hipMemsetAsync(counter, 0, sizeof(int32_t), s);
-  if (e != hipSuccess) return e;
-  if (p->rows > 0)
-    spmm_find_fix<<<(unsigned)((p->rows + 255) / 256), 256, 0, s>>>(p->rowptr, p->rows, p->chunk,
-                                                                     fix_rows_buf, counter);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  int32_t n = 0;
-  e = hipMemcpyAsync(&n, counter, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+int spmm_item_nnz(int64_t nnz) {
+  (void)nnz;
+  return 128;
+}
+
+SpmmSizes spmm_sizes(int64_t rows, int64_t nnz, int L) {
+  SpmmSizes z;
+  z.items = rows + 2 * (nnz / L) + 2;
+  z.fix = nnz / L + 1;
+  z.seg = 2 * (nnz / L) + 2;
+  return z;
+}
+
+hipError_t spmm_build(SpmmPlan* p, hipStream_t s) {
+  const int64_t rows = p->rows;
+  const int L = p->L;
+  std::vector<int32_t> rp((size_t)rows + 1);
+  hipError_t e = hipMemcpyAsync(rp.data(), p->rowptr, rp.size() * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s);
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(s);
-  p->n_fix = n;
-  (void)K;
-  return e;
+  if (e != hipSuccess) return e;
+  std::vector<int4> items;
+  std::vector<int32_t> slot, fix;
+  int32_t nseg = 0;
+  int64_t r = 0;
+  while (r < rows) {
+    const int64_t len = (int64_t)rp[r + 1] - rp[r];
+    if (len > L) {  // a long row: segments of L nonzeros, summed by the fixup pass
+      const int32_t first = nseg;
+      int32_t cnt = 0;
+      for (int64_t j = rp[r]; j < rp[r + 1]; j += L) {
+        const int64_t je = std::min<int64_t>(j + L, rp[r + 1]);
+        items.push_back(make_int4((int)r, (int)r + 1, (int)j, (int)je));
+        slot.push_back(nseg++);
+        cnt++;
+      }
+      fix.push_back((int32_t)r);
+      fix.push_back(first);
+      fix.push_back(cnt);
+      r++;
+      continue;
+    }
+    const int64_t r0 = r, j0 = rp[r];
+    while (r < rows && r - r0 < kMaxRowsPerItem && (int64_t)rp[r + 1] - rp[r] <= L &&
+           (int64_t)rp[r + 1] - j0 <= L)
+      r++;
+    items.push_back(make_int4((int)r0, (int)r, (int)j0, (int)rp[r]));
+    slot.push_back(-1);
+  }
+  const SpmmSizes cap = spmm_sizes(rows, p->nnz, L);
+  if ((int64_t)items.size() > cap.items || (int64_t)fix.size() / 3 > cap.fix || nseg > cap.seg)
+    return hipErrorInvalidValue;  // cannot happen: the bounds cover every partition
+  p->n_items = (int64_t)items.size();
+  p->n_fix = (int64_t)fix.size() / 3;
+  p->n_seg = nseg;
+  if (!items.empty()) {
+    e = hipMemcpyAsync(p->items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(p->item_slot, slot.data(), slot.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  if (!fix.empty()) {
+    e = hipMemcpyAsync(p->fix, fix.data(), fix.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipStreamSynchronize(s);  // the host vectors go out of scope
 }
 
 hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hipStream_t s) {
@@ -231,13 +239,12 @@ hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hip
   a.rowptr = p.rowptr;
   a.col = p.col;
   a.val = p.val;
-  a.chunk_row = p.chunk_row;
+  a.items = p.items;
+  a.slot = p.item_slot;
   a.X = X;
   a.out = out;
   a.carry = p.carry;
-  a.nnz = p.nnz;
-  a.nchunks = p.nchunks;
-  a.chunk = p.chunk;
+  a.n_items = p.n_items;
   a.K = K;
   const size_t esz = t == Elem::F32 ? 4 : 2;
   const bool vec = (K % 4 == 0) && (((uintptr_t)X) % (4 * esz) == 0);
@@ -245,8 +252,7 @@ hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hip
                                 : launch_k<__bf16, __bf16>(a, vec, s);
   if (e != hipSuccess) return e;
   if (p.n_fix > 0) {
-    spmm_fixup<<<(unsigned)((p.n_fix + 3) / 4), 256, 0, s>>>(p.rowptr, p.fix_rows, p.n_fix, p.carry,
-                                                              out, K, p.chunk);
+    spmm_fixup<<<(unsigned)((p.n_fix + 3) / 4), 256, 0, s>>>(p.fix, p.n_fix, p.carry, out, K);
     e = hipGetLastError();
   }
   return e;
