@@ -81,7 +81,7 @@ typedef struct nmf_info {
   int64_t V, D, nnz;
   int32_t K, format, precision;
   int32_t tile;           /* tile width T of the column-update kernels              */
-  int32_t w_groups;       /* workgroups of the persistent W-update kernel           */
+  int32_t w_groups;       /* column groups (phase 2, norm exchange) of the W kernel  */
   int32_t h_groups;       /* workgroups of the H-update kernel                      */
   int64_t sweeps_done;
 } nmf_info;

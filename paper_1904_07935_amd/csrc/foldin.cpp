@@ -230,7 +230,6 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
   a.K = K;
   a.eps = p->eps;
   a.diag_one = 1;
-  a.status = p->status;
   int filled = 0;  // trace entries waiting in f.trace
   int written = 0; // trace entries copied to the host
   auto flush = [&]() -> int {
@@ -248,7 +247,7 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
     filled++;
   }
   for (int i = 0; i < n_sweeps; i++) {
-    FCHECK(hals_update(a, false, 0, s));
+    FCHECK(hals_update(a, s));
     if (rel_trace) {
       if (filled == kTraceChunk) {
         rc = flush();

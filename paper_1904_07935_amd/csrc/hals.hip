@@ -18,21 +18,34 @@
 // of phase 1, Eq. 4), and inside the tile the old values of l > t plus the
 // diagonal.  Done in place, one product per tile replaces both GEMM phases.
 // Its B operand (G's tile columns with the in-tile mask and diagonal folded
-// in) is staged once per tile in LDS; the A operand (this group's rows of X)
-// streams from global memory in double-buffered register chunks.  What remains
-// is phase 2 (Eq. 5 with +P, as in Alg. 2): within the tile, column by column,
-// clip, normalise (W), and apply the new value to the tile's later columns.
+// in) is staged once per tile in LDS; the A operand (rows of X) streams from
+// global memory in double-buffered register chunks.  What remains is phase 2
+// (Eq. 5 with +P, as in Alg. 2): within the tile, column by column, clip,
+// normalise (W), and apply the new value to the tile's later columns.
 //
-// The W half needs the L2 norm of each finished column over all rows before
-// the next column can be clipped (Alg. 1 normalises inside the k loop), so the
-// W kernel is persistent: its workgroups are co-resident (cooperative launch)
-// and exchange one FP32 partial per column through tagged 64-bit slots.  Every
-// workgroup sums all partials in the same fixed order, so every workgroup (and
-// every run) gets the bitwise-identical norm; the paper's atomicAdd of partial
-// sums (Alg. 4) would be order-dependent.  Only the update of the next column
-// sits between two exchanges; the rest of the in-tile work runs while the
-// exchange is in flight.  Waits are bounded: on a timeout a status bit is set,
-// every group stops waiting, and the kernel still runs to completion.
+// H half: rows are independent, so each workgroup runs the whole sweep over a
+// slab of 32 rows (product and phase 2 per tile, in LDS).
+//
+// W half: each column needs the L2 norm of the finished column over all rows
+// before the next column can be clipped (Alg. 1 normalises inside the k
+// loop), so phase 2 is a chain of K chip-level reductions and their latency,
+// not arithmetic, bounds the kernel.  One cooperative launch of one 512-thread
+// workgroup per CU splits the work by role:
+//   * column groups (few, about 2048 rows each) hold the tile's 32 columns of
+//     their rows in registers and run phase 2, exchanging one FP32 partial per
+//     column through tagged 64-bit slots.  They are the workgroups whose index
+//     is a multiple of 8 (then 8i+1, ...): the dispatcher places workgroup b on
+//     XCD b % 8, so up to 32 column groups share one XCD and its L2, where the
+//     exchange round trip is shortest.  Placement only affects speed.
+//   * product groups (all others) compute the tile product of every row into
+//     a [rows, 32] hand-off buffer once the column groups have published the
+//     previous tile (the product reads those new columns).
+// Every column group sums all partials in the same fixed order, so all of them
+// (and every run) get the bitwise-identical norm; the paper's atomicAdd of
+// partial sums (Alg. 4) would be order-dependent.  Hand-offs between roles are
+// tagged flags over device-scope (XCD-coherent) loads and stores.  All waits are
+// bounded: on a timeout a status bit is set, every group stops waiting, and
+// the kernel still runs to completion.
 #include "internal.hpp"
 
 namespace plnmf {
@@ -40,35 +53,11 @@ namespace {
 
 constexpr int T = kTile;
 constexpr int TP = T + 1;  // LDS row pitch (bank spread)
-constexpr int kMaxRowsW = 512;
 constexpr int kRowsH = 32;
 
-// dynamic LDS layout (floats): xt [rows][TP] | gt [T][TP] | part [4][32][TP] |
-// bp [Kp][TP] | red [8], with Kp = K rounded up to a multiple of 8 (the product
-// reads the contraction in groups of 8; rows >= K of bp hold zeros)
-struct Smem {
-  float* xt;
-  float* gt;
-  float* part;
-  float* bp;
-  float* red;
-};
+// --------------------------------------------------------- shared pieces ----
 
 __host__ __device__ inline int kpad(int K) { return (K + 7) / 8 * 8; }
-
-__host__ __device__ inline size_t smem_floats(int rows, int K) {
-  return (size_t)rows * TP + (size_t)T * TP + 4 * 32 * TP + (size_t)kpad(K) * TP + 8;
-}
-
-__device__ __forceinline__ Smem carve(float* base, int rows, int K) {
-  Smem s;
-  s.xt = base;
-  s.gt = s.xt + rows * TP;
-  s.part = s.gt + T * TP;
-  s.bp = s.part + 4 * 32 * TP;
-  s.red = s.bp + kpad(K) * TP;
-  return s;
-}
 
 __device__ __forceinline__ unsigned long long pack_slot(unsigned tag, float v) {
   return ((unsigned long long)tag << 32) | (unsigned long long)__float_as_uint(v);
@@ -84,13 +73,18 @@ __device__ __forceinline__ void publish(unsigned long long* slots, int groups, i
                      pack_slot(tag, mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Chip-wide fixed-order sum of the published partials (wave 0, all lanes).
-__device__ float collect_sum(const unsigned long long* slots, int groups, int g, unsigned tag,
-                             int par, int32_t* status) {
+__device__ __forceinline__ bool timed_out(const int32_t* status) {
+  return (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 256) != 0;
+}
+
+// Fixed-order sum of the published partials of all groups (wave 0, all lanes),
+// groups <= 64 * MAXS.
+template <int MAXS>
+__device__ __forceinline__ float collect_sum(const unsigned long long* slots, int groups, int g,
+                                             unsigned tag, int par, int32_t* status) {
   const int lane = threadIdx.x & 63;
   const unsigned long long* base =
       slots + (int64_t)(g % kSlotReplicas) * kSlotStride + (int64_t)par * groups;
-  constexpr int MAXS = 16;  // groups <= 1024
   unsigned long long v[MAXS];
   int spins = 0;
   bool done;
@@ -105,9 +99,7 @@ __device__ float collect_sum(const unsigned long long* slots, int groups, int g,
       }
     }
     // give up at once if any workgroup already timed out (bounded total wait)
-    if (!done && (++spins & 255) == 0 &&
-        (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 256))
-      break;
+    if (!done && (++spins & 255) == 0 && timed_out(status)) break;
   } while (!done && spins < kSpinLimit);
   if (!done) atomicOr(status, 256);
   float t = 0.0f;
@@ -117,6 +109,92 @@ __device__ float collect_sum(const unsigned long long* slots, int groups, int g,
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
   return t;
+}
+
+// Sum over all 64 lanes, the same in every lane, in a fixed order: DPP steps
+// within each row of 16 lanes (lane pairs, quads, halves), then the four row
+// sums in row order.  VALU data movement only (no LDS round trips).
+__device__ __forceinline__ float wave_sum(float v) {
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x141, 0xF, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x140, 0xF, 0xF, false));
+  const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+  const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+  const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+  const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+  return ((r0 + r1) + r2) + r3;
+}
+
+// The same as collect_sum for at most 64 groups (one slot per lane), with the
+// lanes summed by wave_sum.
+__device__ __forceinline__ float collect_sum64(const unsigned long long* slots, int groups, int g,
+                                               unsigned tag, int par, int32_t* status) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long* p =
+      slots + (int64_t)(g % kSlotReplicas) * kSlotStride + (int64_t)par * groups + lane;
+  const bool act = lane < groups;
+  unsigned long long v = (unsigned long long)tag << 32;  // inactive lanes: ready, zero
+  int spins = 0;
+  bool done;
+  do {
+    if (act) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    done = __all((unsigned)(v >> 32) == tag);
+    if (!done && (++spins & 255) == 0 && timed_out(status)) break;
+  } while (!done && spins < kSpinLimit);
+  if (!done && lane == 0) atomicOr(status, 256);
+  return wave_sum(__uint_as_float((unsigned)v));
+}
+
+// Bounded wait of one wave until flags[i * stride], i < n, all hold `tag`.
+__device__ void wait_flags(const unsigned* flags, int n, int stride, unsigned tag, int32_t* status) {
+  const int lane = threadIdx.x & 63;
+  int spins = 0;
+  bool done;
+  do {
+    done = true;
+    for (int i = lane; i < n; i += 64)
+      done = done && (__hip_atomic_load(flags + (int64_t)i * stride, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT) == tag);
+    if (!done && (++spins & 255) == 0 && timed_out(status)) break;
+  } while (!done && spins < kSpinLimit);
+  if (!done) atomicOr(status, 256);
+}
+
+// Hand-off data between workgroups of the W kernel: every tile has its own
+// region of the hand-off buffers, so each of their cache lines is written once
+// per launch, by device-scope stores (the sc1 cache policy, written through
+// past the XCD's own L2), and read only after the producer's flag.  No XCD can
+// hold a stale copy of such a line (caches are invalidated at kernel start and
+// nobody reads the line earlier), so the readers use plain cached loads and no
+// L2 write-back or invalidation is needed.  The producer waits until its
+// stores are complete before it raises the flag.
+constexpr int kThrough = 16;  // buffer cache-policy bit sc1 (device scope)
+
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t store_view(void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void st_through4(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, floatx4 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(uintx4, v), r, byte_off, 0, kThrough);
+}
+__device__ __forceinline__ void st_through(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, byte_off, 0, kThrough);
+}
+
+// Every thread: wait for its stores to complete; then one thread raises the flag.
+__device__ __forceinline__ void signal_flag(unsigned* flag, unsigned tag) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave 0 waits for the flags; the barrier keeps every later load after it.
+__device__ __forceinline__ void await_flags(const unsigned* flags, int n, int stride, unsigned tag,
+                                            int32_t* status) {
+  if ((threadIdx.x >> 6) == 0) wait_flags(flags, n, stride, tag, status);
+  __syncthreads();
 }
 
 // B operand of the tile product: contraction row l, output column c of the tile [a0, b0).
@@ -133,7 +211,7 @@ constexpr int CH = 8;  // float4 groups (of 8 contraction indices) per register 
 
 template <bool VEC>
 __device__ __forceinline__ void load_chunk(floatx4 (&buf)[CH], const float* __restrict__ xr, bool rok,
-                                           int l0, int le, int K, int h) {
+                                           int l0, int le, int h) {
 #pragma unroll
   for (int gi = 0; gi < CH; gi++) {
     const int lc = l0 + 8 * gi + 4 * h;
@@ -162,38 +240,97 @@ __device__ __forceinline__ void mfma_chunk(const floatx4 (&buf)[CH], const float
   }
 }
 
-// The tile product for every row of this group into xt (Bterm added).
+// One wave: the 32 x 32 product of rows xr (this lane's row, lane % 32) over
+// contraction [lb, le) with the LDS panel bp.  Lane holds result row
+// 8 j + 4 (lane / 32) + i, column lane % 32, in acc[4 j + i].
 template <bool VEC>
-__device__ void tile_product(const HalsArgs& a, const Smem& sm, int64_t row0, int64_t row1, int nr,
-                             int a0, int tw) {
+__device__ __forceinline__ floatx16 block_product(const float* __restrict__ xr, bool rok, int lb,
+                                                  int le, const float* __restrict__ bp, int lane) {
+  const int h = lane >> 5;
+  floatx16 acc;
+#pragma unroll
+  for (int e = 0; e < 16; e++) acc[e] = 0.0f;
+  floatx4 b0[CH], b1[CH];
+  if (lb < le) load_chunk<VEC>(b0, xr, rok, lb, le, h);
+  for (int l0 = lb; l0 < le; l0 += 2 * 8 * CH) {
+    const int l1 = l0 + 8 * CH;
+    if (l1 < le) load_chunk<VEC>(b1, xr, rok, l1, le, h);
+    mfma_chunk(b0, bp, l0, le, lane, acc);
+    const int l2 = l1 + 8 * CH;
+    if (l2 < le) load_chunk<VEC>(b0, xr, rok, l2, le, h);
+    if (l1 < le) mfma_chunk(b1, bp, l1, le, lane, acc);
+  }
+  return acc;
+}
+
+// Staging of the tile's G block gt [T][TP] and of the product's B panel
+// bp [kpad(K)][TP] (bm_value) by NT threads, eight loads in flight per thread.
+constexpr int kStageU = 8;
+
+template <int NT>
+__device__ __forceinline__ void stage_gt(const float* __restrict__ G, int K, int a0, int tw, float* gt) {
+  const int tid = threadIdx.x;
+  for (int i0 = 0; i0 < T * T; i0 += NT * kStageU) {
+    float v[kStageU];
+#pragma unroll
+    for (int u = 0; u < kStageU; u++) {
+      const int i = i0 + tid + NT * u, r = i / T, c = i % T;
+      v[u] = (i < T * T && r < tw && c < tw) ? G[(int64_t)(a0 + r) * K + a0 + c] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageU; u++) {
+      const int i = i0 + tid + NT * u;
+      if (i < T * T) gt[(i / T) * TP + i % T] = v[u];
+    }
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void stage_bp(const float* __restrict__ G, int K, int a0, int b0,
+                                         int diag_one, float* bp) {
+  const int tid = threadIdx.x;
+  const int n = kpad(K) * T;
+  for (int i0 = 0; i0 < n; i0 += NT * kStageU) {
+    float v[kStageU];
+#pragma unroll
+    for (int u = 0; u < kStageU; u++) {
+      const int i = i0 + tid + NT * u;
+      v[u] = i < n ? bm_value(G, K, i / T, a0 + i % T, a0, b0, diag_one) : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageU; u++) {
+      const int i = i0 + tid + NT * u;
+      if (i < n) bp[(i / T) * TP + i % T] = v[u];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- H half ----
+
+// dynamic LDS (floats): xt [32][TP] | gt [T][TP] | part [4][32][TP] | bp [Kp][TP],
+// Kp = K rounded up to a multiple of 8 (rows >= K of bp hold zeros)
+__host__ __device__ inline size_t h_smem_floats(int K) {
+  return (size_t)kRowsH * TP + (size_t)T * TP + 4 * 32 * TP + (size_t)kpad(K) * TP;
+}
+
+// The tile product of this group's rows into xt (Bterm added).  With fewer
+// than four 32-row blocks the contraction is split over the idle waves.
+template <bool VEC>
+__device__ void h_tile_product(const HalsArgs& a, float* xt, float* part, const float* bp,
+                               int64_t row0, int64_t row1, int nr, int a0, int tw) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int K = a.K;
   const int nrb = (nr + 31) / 32;
   const int parts = nrb >= 4 ? 1 : (nrb == 2 ? 2 : (nrb == 1 ? 4 : 1));
-  const int chunk = ((K + parts - 1) / parts + 63) / 64 * 64;
+  const int chunk = ((K + parts - 1) / parts + 7) / 8 * 8;  // multiple of 8: MFMA k-groups
   const int h = lane >> 5;
-  const float* __restrict__ X = a.X;
   for (int job = w; job < nrb * parts; job += 4) {
     const int rb = job / parts, p = job % parts;
     const int lb = p * chunk;
     const int le = lb + chunk < K ? lb + chunk : K;
     const int64_t r = row0 + rb * 32 + (lane & 31);
     const bool rok = r < row1;
-    const float* xr = X + (rok ? r : row0) * K;
-    floatx16 acc;
-#pragma unroll
-    for (int e = 0; e < 16; e++) acc[e] = 0.0f;
-    floatx4 b0[CH], b1[CH];
-    if (lb < le) load_chunk<VEC>(b0, xr, rok, lb, le, K, h);
-    for (int l0 = lb; l0 < le; l0 += 2 * 8 * CH) {
-      const int l1 = l0 + 8 * CH;
-      if (l1 < le) load_chunk<VEC>(b1, xr, rok, l1, le, K, h);
-      mfma_chunk(b0, sm.bp, l0, le, lane, acc);
-      const int l2 = l1 + 8 * CH;
-      if (l2 < le) load_chunk<VEC>(b0, xr, rok, l2, le, K, h);
-      if (l1 < le) mfma_chunk(b1, sm.bp, l1, le, lane, acc);
-    }
-    // lane holds y[rb*32 + 8 j + 4 h + i][lane%32]
+    const floatx16 acc = block_product<VEC>(a.X + (rok ? r : row0) * K, rok, lb, le, bp, lane);
     if (parts == 1) {
 #pragma unroll
       for (int j = 0; j < 4; j++)
@@ -201,13 +338,13 @@ __device__ void tile_product(const HalsArgs& a, const Smem& sm, int64_t row0, in
         for (int i = 0; i < 4; i++) {
           const int rl = rb * 32 + 8 * j + 4 * h + i;
           const int cl = lane & 31;
-          if (rl < nr && cl < tw) sm.xt[rl * TP + cl] = acc[4 * j + i] + a.Bterm[(row0 + rl) * K + a0 + cl];
+          if (rl < nr && cl < tw) xt[rl * TP + cl] = acc[4 * j + i] + a.Bterm[(row0 + rl) * K + a0 + cl];
         }
     } else {
 #pragma unroll
       for (int j = 0; j < 4; j++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) sm.part[(w * 32 + 8 * j + 4 * h + i) * TP + (lane & 31)] = acc[4 * j + i];
+        for (int i = 0; i < 4; i++) part[(w * 32 + 8 * j + 4 * h + i) * TP + (lane & 31)] = acc[4 * j + i];
     }
   }
   if (parts > 1) {
@@ -216,138 +353,449 @@ __device__ void tile_product(const HalsArgs& a, const Smem& sm, int64_t row0, in
       const int rl = i / tw, cl = i % tw;
       const int rb = rl / 32;
       float v = a.Bterm[(row0 + rl) * K + a0 + cl];
-      for (int p = 0; p < parts; p++) v += sm.part[((rb * parts + p) * 32 + rl % 32) * TP + cl];
-      sm.xt[rl * TP + cl] = v;
+      for (int p = 0; p < parts; p++) v += part[((rb * parts + p) * 32 + rl % 32) * TP + cl];
+      xt[rl * TP + cl] = v;
     }
   }
 }
 
-template <bool NORM, bool VEC>
-__global__ __launch_bounds__(256) void hals_kernel(HalsArgs a) {
+template <bool VEC>
+__global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
   extern __shared__ float smem_raw[];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int K = a.K;
-  const int g = blockIdx.x, groups = gridDim.x;
-  const int64_t row0 = (int64_t)g * a.rows_per_group;
-  int64_t row1 = row0 + a.rows_per_group;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsH;
+  int64_t row1 = row0 + kRowsH;
   if (row1 > a.rows) row1 = a.rows;
   const int nr = row0 < row1 ? (int)(row1 - row0) : 0;
-  const Smem sm = carve(smem_raw, a.rows_per_group, K);
+  float* xt = smem_raw;
+  float* gt = xt + kRowsH * TP;
+  float* part = gt + T * TP;
+  float* bp = part + 4 * 32 * TP;
   float* __restrict__ X = a.X;
   const float eps = a.eps;
 
   for (int a0 = 0; a0 < K; a0 += T) {
     const int b0 = a0 + T < K ? a0 + T : K;
     const int tw = b0 - a0;
-    for (int i = tid; i < T * T; i += 256) {
-      const int r = i / T, c = i % T;
-      sm.gt[r * TP + c] = (r < tw && c < tw) ? a.G[(int64_t)(a0 + r) * K + a0 + c] : 0.0f;
-    }
-    for (int i = tid; i < kpad(K) * T; i += 256) {
-      const int l = i / T, c = i % T;
-      sm.bp[l * TP + c] = bm_value(a.G, K, l, a0 + c, a0, b0, a.diag_one);
-    }
+    stage_gt<256>(a.G, K, a0, tw, gt);
+    stage_bp<256>(a.G, K, a0, b0, a.diag_one, bp);
     __syncthreads();
-    tile_product<VEC>(a, sm, row0, row1, nr, a0, tw);
+    h_tile_product<VEC>(a, xt, part, bp, row0, row1, nr, a0, tw);
     __syncthreads();
 
-    if constexpr (!NORM) {
-      // eight threads per row, each owning four of the tile's columns
-      const int rl = tid >> 3, j = tid & 7;
+    // phase 2: one thread per row with the tile's 32 columns in registers
+    if (tid < kRowsH) {
+      const int rl = tid;
       const bool rok = rl < nr;
-      float y[4];
+      float y[T];
 #pragma unroll
-      for (int e = 0; e < 4; e++) y[e] = rok ? sm.xt[rl * TP + 4 * j + e] : 0.0f;
+      for (int c = 0; c < T; c++) y[c] = rok ? xt[rl * TP + c] : 0.0f;
 #pragma unroll
       for (int t = 0; t < T; t++) {
         if (t < tw) {
-          const int jt = t >> 2, et = t & 3;
-          float x = 0.0f;
-          if (j == jt) {
-            x = fmaxf(eps, y[et]);
-            y[et] = x;
-          }
-          x = __shfl(x, (lane & ~7) | jt);
+          const float x = fmaxf(eps, y[t]);
+          y[t] = x;
 #pragma unroll
-          for (int e = 0; e < 4; e++)
-            if (4 * j + e > t) y[e] -= x * sm.gt[t * TP + 4 * j + e];
+          for (int c = t + 1; c < T; c++) y[c] -= x * gt[t * TP + c];
         }
       }
       if (rok) {
 #pragma unroll
-        for (int e = 0; e < 4; e++) sm.xt[rl * TP + 4 * j + e] = y[e];
-      }
-    } else {
-      constexpr int RPT = (kMaxRowsW + 255) / 256;  // rows per thread
-      // invariant at step t: xt[r][t] = u_t (clipped, not normalised), ss = my
-      // partial of sum u_t^2; columns > t lack only the pending x_{t-1} term
-      float ss = 0.0f;
-#pragma unroll
-      for (int q = 0; q < RPT; q++) {
-        const int rl = tid + 256 * q;
-        if (rl < nr) {
-          const float u = fmaxf(eps, sm.xt[rl * TP]);
-          sm.xt[rl * TP] = u;
-          ss += u * u;
-        }
-      }
-      float xprev[RPT];
-#pragma unroll
-      for (int q = 0; q < RPT; q++) xprev[q] = 0.0f;
-      for (int t = 0; t < tw; t++) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
-        if (lane == 0) sm.red[w] = ss;
-        __syncthreads();
-        const unsigned tag = (a.epoch << 10) | (unsigned)(a0 + t);
-        const int par = (a0 + t) & 1;
-        if (tid < kSlotReplicas)
-          publish(a.slots, groups, g, tag, par, sm.red[0] + sm.red[1] + sm.red[2] + sm.red[3], tid);
-        // off the critical path: the previous column's contribution to columns > t
-        if (t > 0) {
-#pragma unroll
-          for (int q = 0; q < RPT; q++) {
-            const int rl = tid + 256 * q;
-            if (rl < nr)
-              for (int c = t + 1; c < tw; c++) sm.xt[rl * TP + c] -= xprev[q] * sm.gt[(t - 1) * TP + c];
-          }
-        }
-        if (w == 0) {
-          const float tot = collect_sum(a.slots, groups, g, tag, par, a.status);
-          if (lane == 0) sm.red[4] = tot;
-        }
-        __syncthreads();
-        const float nrm = sqrtf(sm.red[4]);
-        ss = 0.0f;
-#pragma unroll
-        for (int q = 0; q < RPT; q++) {
-          const int rl = tid + 256 * q;
-          if (rl < nr) {
-            const float x = sm.xt[rl * TP + t] / nrm;
-            sm.xt[rl * TP + t] = x;
-            xprev[q] = x;
-            if (t + 1 < tw) {
-              const float u = fmaxf(eps, sm.xt[rl * TP + t + 1] - x * sm.gt[t * TP + t + 1]);
-              sm.xt[rl * TP + t + 1] = u;
-              ss += u * u;
-            }
-          }
-        }
+        for (int c = 0; c < T; c++) xt[rl * TP + c] = y[c];
       }
     }
     __syncthreads();
     // write the finished tile back (rows are K-contiguous)
     for (int i = tid; i < nr * tw; i += 256) {
       const int rl = i / tw, cl = i % tw;
-      X[(row0 + rl) * K + a0 + cl] = sm.xt[rl * TP + cl];
+      X[(row0 + rl) * K + a0 + cl] = xt[rl * TP + cl];
     }
     __syncthreads();
   }
 }
 
-template <bool NORM, bool VEC>
-const void* kernel_ptr() {
-  return (const void*)hals_kernel<NORM, VEC>;
+// ---------------------------------------------------------------- W half ----
+
+constexpr int kWThreads = 512;
+constexpr int kWWaves = kWThreads / 64;
+constexpr int kWRowThreads = kWThreads - 64;        // wave 0 of a column group runs the exchange
+constexpr int kWMaxRpt = 4;                         // rows per row thread of a column group
+constexpr int kWMaxRows = kWRowThreads * kWMaxRpt;  // rows per column group
+constexpr size_t kWSmemMin = 82 * 1024;             // > half the LDS: one group per CU
+constexpr int kWMaxColGroups = 64;
+
+// LDS (floats).  Column role: gt [T][TP] | wave slots [2][kWWaves] | total slots [2] (u64) |
+// lane partials [2][kWWaves - 1][64].  Product role: bp [kpad(K)][TP] | per-wave
+// stash [kWWaves][jobs per wave][32][TP] (partial products, then the transpose).
+constexpr size_t kLdsMax = 160 * 1024;
+
+__host__ __device__ inline size_t w_smem_bytes(int K, int jpw) {
+  size_t b = ((size_t)kpad(K) * TP + (size_t)kWWaves * jpw * 32 * TP) * 4;
+  const size_t col = (size_t)T * TP * 4 + (2 * kWWaves + 2) * 8 + 2 * (kWWaves - 1) * 64 * 4;
+  if (b < col) b = col;
+  return b < kWSmemMin ? kWSmemMin : b;
+}
+
+__device__ __forceinline__ unsigned tile_tag(unsigned epoch, int j) { return (epoch << 10) | (unsigned)j; }
+
+// Rank of workgroup b when the grid is ordered XCD-major: b % 8 first, then b / 8.
+__device__ __forceinline__ int xcd_major_rank(int b, int grid) {
+  int key = b >> 3;
+  for (int m = 0; m < (b & 7); m++) key += (grid - m + 7) >> 3;
+  return key;
+}
+
+// Hand-off layout: tile j of Y (the product) and of Wn (the finished columns)
+// is stored column-quad-major, float4 (j, v, r) = columns 4v..4v+3 of row r at
+// float4 index (j * 8 + v) * rows + r, so that a wave's rows are contiguous.
+__device__ __forceinline__ int64_t quad_index(int64_t rows, int j, int v, int64_t r) {
+  return ((int64_t)j * (T / 4) + v) * rows + r;
+}
+
+// Bounded wait of one wave for a tagged LDS slot; returns its value.
+__device__ __forceinline__ float lds_wait(unsigned long long* slot, unsigned tag, int32_t* status) {
+  unsigned long long v;
+  int spins = 0;
+  do {
+    v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  } while ((unsigned)(v >> 32) != tag && ++spins < kSpinLimit);
+  if ((unsigned)(v >> 32) != tag && (threadIdx.x & 63) == 0) atomicOr(status, 256);
+  return __uint_as_float((unsigned)v);
+}
+
+__device__ __forceinline__ void lds_post(unsigned long long* slot, unsigned tag, float v) {
+  __hip_atomic_store(slot, pack_slot(tag, v), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Column groups.  Waves 1..7 hold rows (RPT per thread) and run phase 2; wave
+// 0 runs the column-norm exchange: it sums the row waves' partials (tagged LDS
+// slots, wave order), publishes the group's partial, sums all groups'
+// partials and posts the total back in LDS.  No workgroup barrier separates
+// two columns, and the exchange wave starts polling as soon as it has
+// published, while the row waves apply the previous column to the rest of
+// the tile.  LOCAL: a single column group, no exchange between groups.
+template <int RPT, bool VEC, bool LOCAL>
+__device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n_prod, float* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const bool xwave = w == 0;
+  const int K = a.K;
+  const int64_t rows = a.rows;
+  float* gt = lds;  // [T][TP] G of the tile
+  unsigned long long* lpart = (unsigned long long*)(lds + T * TP);  // [2][kWWaves]
+  unsigned long long* ltot = lpart + 2 * kWWaves;                   // [2]
+  float* lvals = (float*)(ltot + 2);                                // [2][kWWaves - 1][64]
+  const int64_t row0 = (int64_t)rank * a.rows_per_group;
+  int64_t row1 = row0 + a.rows_per_group;
+  if (row1 > rows) row1 = rows;
+  const float eps = a.eps;
+  const floatx4* __restrict__ Y4 = (const floatx4*)a.Y;
+  const __amdgpu_buffer_rsrc_t wnview = store_view(a.Wn, (int64_t)((K + T - 1) / T) * rows * T * 4);
+  bool valid[RPT];
+  int64_t rr[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; q++) {
+    rr[q] = row0 + (tid - 64) + kWRowThreads * q;
+    valid[q] = !xwave && rr[q] < row1;
+  }
+  float y[RPT][T];
+  if (tid < 2 * kWWaves + 2) lpart[tid] = 0;  // no stale tags (the first barrier below orders it)
+
+  for (int j = 0, a0 = 0; a0 < K; j++, a0 += T) {
+    const int tw = a0 + T < K ? T : K - a0;
+    __syncthreads();  // gt of the previous tile is no longer read
+    stage_gt<kWThreads>(a.G, K, a0, tw, gt);
+    // the product groups serving this column group: rank, rank + n_col, ...
+    await_flags(a.flags + rank, (n_prod - rank + a.n_col - 1) / a.n_col, a.n_col,
+                tile_tag(a.epoch, j), a.status);
+    if (xwave) {
+      for (int t = 0; t < tw; t++) {
+        const unsigned ctag = (a.epoch << 10) | (unsigned)(a0 + t);
+        const int par = (a0 + t) & 1;
+        if (lane >= 1 && lane < kWWaves) lds_wait(lpart + par * kWWaves + lane, ctag, a.status);
+        // the group's partial: per lane over the row waves in order, then across lanes
+        float g = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kWWaves - 1; i++) g += lvals[(par * (kWWaves - 1) + i) * 64 + lane];
+        g = wave_sum(g);
+        float tot = g;
+        if constexpr (!LOCAL) {
+          if (lane < kSlotReplicas) publish(a.slots, a.n_col, rank, ctag, par, g, lane);
+          tot = collect_sum64(a.slots, a.n_col, rank, ctag, par, a.status);
+        }
+        if (lane == 0) lds_post(ltot + par, ctag, tot);
+      }
+    } else {
+      // this group's rows of the tile's product (one contiguous run of rows per wave)
+#pragma unroll
+      for (int q = 0; q < RPT; q++) {
+#pragma unroll
+        for (int v = 0; v < T / 4; v++) {
+          const floatx4 f = valid[q] ? Y4[quad_index(rows, j, v, rr[q])] : floatx4{0, 0, 0, 0};
+#pragma unroll
+          for (int e = 0; e < 4; e++) y[q][4 * v + e] = f[e];
+        }
+      }
+      // invariant at step t: y[q][t] = u_t (clipped, not normalised) and ss = this
+      // thread's part of sum u_t^2; columns > t lack only the pending x_{t-1} term
+      float ss = 0.0f;
+#pragma unroll
+      for (int q = 0; q < RPT; q++) {
+        const float u = fmaxf(eps, y[q][0]);
+        y[q][0] = u;
+        ss += valid[q] ? u * u : 0.0f;
+      }
+      float xprev[RPT];
+#pragma unroll
+      for (int q = 0; q < RPT; q++) xprev[q] = 0.0f;
+#pragma unroll
+      for (int t = 0; t < T; t++) {
+        if (t < tw) {
+          const unsigned ctag = (a.epoch << 10) | (unsigned)(a0 + t);
+          const int par = (a0 + t) & 1;
+          lvals[(par * (kWWaves - 1) + (w - 1)) * 64 + lane] = ss;
+          if (lane == 0) lds_post(lpart + par * kWWaves + w, ctag, 0.0f);
+          // off the critical path: the previous column's contribution to columns > t
+          if (t > 0) {
+#pragma unroll
+            for (int c = t + 1; c < T; c++) {
+              const float gv = gt[(t - 1) * TP + c];
+#pragma unroll
+              for (int q = 0; q < RPT; q++) y[q][c] -= xprev[q] * gv;
+            }
+          }
+          const float gnext = t + 1 < T ? gt[t * TP + t + 1] : 0.0f;
+          const float tot = lds_wait(ltot + par, ctag, a.status);
+          const float rn = 1.0f / sqrtf(tot);
+          ss = 0.0f;
+#pragma unroll
+          for (int q = 0; q < RPT; q++) {
+            const float x = y[q][t] * rn;
+            y[q][t] = x;
+            xprev[q] = x;
+            if (t + 1 < T) {
+              const float u = fmaxf(eps, y[q][t + 1] - x * gnext);
+              y[q][t + 1] = u;
+              ss += valid[q] ? u * u : 0.0f;
+            }
+          }
+        }
+      }
+      // the finished tile to its hand-off region; product groups copy it into X
+#pragma unroll
+      for (int q = 0; q < RPT; q++) {
+        if (!valid[q]) continue;
+#pragma unroll
+        for (int v = 0; v < T / 4; v++)
+          if (4 * v < tw)
+            st_through4(wnview, (uint32_t)(quad_index(rows, j, v, rr[q]) * 16),
+                        floatx4{y[q][4 * v], y[q][4 * v + 1], y[q][4 * v + 2], y[q][4 * v + 3]});
+      }
+    }
+    signal_flag(a.flags + kWFlagCol + rank, tile_tag(a.epoch, j));
+  }
+}
+
+// A operand of the product for tile j, contraction columns [32 s, 32 s + 32):
+// finished tiles (s < j) from their hand-off region, the rest still old in X.
+template <bool VEC>
+__device__ __forceinline__ void load_segment(floatx4 (&buf)[4], const HalsWArgs& a, int64_t r,
+                                             bool rok, int j, int s, int h) {
+  const int K = a.K;
+  if (s < j) {
+    const floatx4* __restrict__ Wn4 = (const floatx4*)a.Wn;
+#pragma unroll
+    for (int gi = 0; gi < 4; gi++)
+      buf[gi] = rok ? Wn4[quad_index(a.rows, s, 2 * gi + h, r)] : floatx4{0, 0, 0, 0};
+  } else {
+    const float* p = a.X + r * K;
+#pragma unroll
+    for (int gi = 0; gi < 4; gi++) {
+      const int lc = T * s + 8 * gi + 4 * h;
+      if constexpr (VEC) {
+        buf[gi] = (rok && lc < K) ? *(const floatx4*)(p + lc) : floatx4{0, 0, 0, 0};
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; e++) buf[gi][e] = (rok && lc + e < K) ? p[lc + e] : 0.0f;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void mfma_segment(const floatx4 (&buf)[4], const float* __restrict__ bp,
+                                             int s, int K, int lane, floatx16& acc) {
+  const int h = lane >> 5, c = lane & 31;
+#pragma unroll
+  for (int gi = 0; gi < 4; gi++) {
+    const int l = T * s + 8 * gi;
+    if (l < K) {
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(buf[gi][e], bp[(l + 4 * h + e) * TP + c], acc, 0, 0, 0);
+    }
+  }
+}
+
+// acc += the product of row block r over every contraction segment but `skip`
+// (off the critical path: one segment in flight at a time keeps registers low).
+template <bool VEC>
+__device__ __forceinline__ void block_segments(floatx16& acc, const HalsWArgs& a, int64_t r, bool rok,
+                                               int j, int nseg, int skip, const float* __restrict__ bp,
+                                               int lane) {
+  const int h = lane >> 5;
+  for (int sg = 0; sg < nseg; sg++) {
+    if (sg == skip) continue;
+    floatx4 buf[4];
+    load_segment<VEC>(buf, a, r, rok, j, sg, h);
+    mfma_segment(buf, bp, sg, a.K, lane, acc);
+  }
+}
+
+// Copy finished tile s (width tws) of rows [rb, re) from its hand-off region
+// into X; part i of np.
+template <bool VEC>
+__device__ __forceinline__ void copy_tile(const HalsWArgs& a, int s, int tws, int64_t rb, int64_t re,
+                                          int i, int np) {
+  const int64_t rows = a.rows;
+  const int K = a.K;
+  const int nv = (tws + 3) / 4;
+  const int64_t nr = re - rb;
+  const floatx4* __restrict__ Wn4 = (const floatx4*)a.Wn;
+  const int64_t n = nr * nv;
+  for (int64_t e = (int64_t)i * kWThreads + threadIdx.x; e < n; e += (int64_t)np * kWThreads) {
+    const int v = (int)(e / nr);
+    const int64_t r = rb + e % nr;
+    const floatx4 f = Wn4[quad_index(rows, s, v, r)];
+    float* dst = a.X + r * K + T * s + 4 * v;
+    if (VEC && 4 * v + 4 <= tws) {
+      *(floatx4*)dst = f;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (4 * v + q < tws) dst[q] = f[q];
+    }
+  }
+}
+
+// Product groups.  Only the previous tile's columns of the product for tile j
+// depend on the column groups' latest output: everything else (Bterm, the old
+// columns in X, the earlier finished tiles) is accumulated before waiting for
+// the previous tile's flags and parked in LDS, so that after them only one
+// 32-column segment of the contraction remains per row block.  Product group p
+// serves column group g = p % n_col (the row blocks of its rows, which are a
+// multiple of 32): it waits for that group's flags only, and that group waits
+// only for its own product groups.
+template <bool VEC>
+__device__ __forceinline__ void w_product_role(const HalsWArgs a, int prank, int n_prod, float* lds) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, c = lane & 31;
+  const int K = a.K;
+  const int jpw = a.jobs_per_wave;
+  float* bp = lds;                                            // [kpad(K)][TP]
+  float* stash = lds + kpad(K) * TP + w * jpw * 32 * TP;      // this wave's [jpw][32][TP]
+  const int64_t rows = a.rows;
+  const int g = prank % a.n_col, gi = prank / a.n_col;
+  const int npg = (n_prod - g + a.n_col - 1) / a.n_col;       // product groups serving g
+  const int64_t grow0 = (int64_t)g * a.rows_per_group;
+  const int64_t grow1 = grow0 + a.rows_per_group < rows ? grow0 + a.rows_per_group : rows;
+  const int64_t blk0 = grow0 / 32;
+  const int64_t nblk = (grow1 - grow0 + 31) / 32;             // row blocks of g
+  const int nseg = (K + T - 1) / T;
+  const __amdgpu_buffer_rsrc_t yview = store_view(a.Y, (int64_t)nseg * rows * T * 4);
+  int j = 0;
+  for (int a0 = 0; a0 < K; j++, a0 += T) {
+    const int b0 = a0 + T < K ? a0 + T : K;
+    const int tw = b0 - a0;
+    __syncthreads();  // the previous tile's products no longer read bp
+    stage_bp<kWThreads>(a.G, K, a0, b0, 0, bp);
+    __syncthreads();
+    // before the wait: Bterm plus every segment but the previous tile's
+    for (int k = 0; k < jpw; k++) {
+      const int64_t lb = ((int64_t)k * kWWaves + w) * npg + gi;
+      if (lb >= nblk) break;
+      const int64_t job = blk0 + lb;
+      floatx16 acc;
+#pragma unroll
+      for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int64_t rg = job * 32 + 8 * jj + 4 * h + i;
+          acc[4 * jj + i] = (c < tw && rg < rows) ? a.Bterm[rg * K + a0 + c] : 0.0f;
+        }
+      const int64_t r = job * 32 + c;
+      const bool rok = r < rows;
+      block_segments<VEC>(acc, a, rok ? r : 0, rok, j, nseg, j - 1, bp, lane);
+      float* st = stash + k * 32 * TP;
+#pragma unroll
+      for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) st[(8 * jj + 4 * h + i) * TP + c] = c < tw ? acc[4 * jj + i] : 0.0f;
+    }
+    if (j > 0) await_flags(a.flags + kWFlagCol + g, 1, 1, tile_tag(a.epoch, j - 1), a.status);
+    for (int k = 0; k < jpw; k++) {
+      const int64_t lb = ((int64_t)k * kWWaves + w) * npg + gi;
+      if (lb >= nblk) break;
+      const int64_t job = blk0 + lb;
+      float* st = stash + k * 32 * TP;
+      if (j > 0) {
+        const int64_t r = job * 32 + c;
+        floatx4 last[4];
+        load_segment<VEC>(last, a, r < rows ? r : 0, r < rows, j, j - 1, h);
+        floatx16 acc;
+#pragma unroll
+        for (int e = 0; e < 16; e++) acc[e] = 0.0f;
+        mfma_segment(last, bp, j - 1, K, lane, acc);
+#pragma unroll
+        for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+            if (c < tw) st[(8 * jj + 4 * h + i) * TP + c] += acc[4 * jj + i];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      // the block in the column-quad layout of Y
+      const int64_t rg = job * 32 + c;
+      if (rg < rows) {
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) {
+          const int v = 4 * h + kk;
+          const float* sp = st + c * TP + 4 * v;
+          st_through4(yview, (uint32_t)(quad_index(rows, j, v, rg) * 16),
+                      floatx4{sp[0], sp[1], sp[2], sp[3]});
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    signal_flag(a.flags + prank, tile_tag(a.epoch, j));
+    // while the column groups run this tile: the previous finished tile into X
+    if (j > 0) copy_tile<VEC>(a, j - 1, T, grow0, grow1, gi, npg);
+  }
+  // the last tile
+  await_flags(a.flags + kWFlagCol + g, 1, 1, tile_tag(a.epoch, j - 1), a.status);
+  copy_tile<VEC>(a, j - 1, K - (j - 1) * T, grow0, grow1, gi, npg);
+}
+
+template <int RPT, bool VEC, bool LOCAL>
+__global__ __launch_bounds__(kWThreads) void hals_w_kernel(HalsWArgs a) {
+  extern __shared__ float lds[];
+  const int key = xcd_major_rank(blockIdx.x, gridDim.x);
+  const int n_prod = (int)gridDim.x - a.n_col;
+  if (key < a.n_col) w_column_role<RPT, VEC, LOCAL>(a, key, n_prod, lds);
+  else w_product_role<VEC>(a, key - a.n_col, n_prod, lds);
+}
+
+template <int RPT, bool VEC, bool LOCAL>
+const void* w_kernel_ptr() {
+  return (const void*)hals_w_kernel<RPT, VEC, LOCAL>;
+}
+
+template <bool LOCAL>
+const void* w_kernel_for_t(int rpt, bool vec) {
+  if (rpt <= 1) return vec ? w_kernel_ptr<1, true, LOCAL>() : w_kernel_ptr<1, false, LOCAL>();
+  if (rpt == 2) return vec ? w_kernel_ptr<2, true, LOCAL>() : w_kernel_ptr<2, false, LOCAL>();
+  return vec ? w_kernel_ptr<4, true, LOCAL>() : w_kernel_ptr<4, false, LOCAL>();
+}
+
+const void* w_kernel_for(int rpt, bool vec, bool local) {
+  return local ? w_kernel_for_t<true>(rpt, vec) : w_kernel_for_t<false>(rpt, vec);
 }
 
 hipError_t allow_smem(const void* fn, size_t bytes) {
@@ -359,56 +807,79 @@ hipError_t allow_smem(const void* fn, size_t bytes) {
 
 int hals_rows_per_group_h() { return kRowsH; }
 
-size_t hals_smem_bytes(int rows_per_group, int K) { return smem_floats(rows_per_group, K) * 4; }
-
-int hals_w_groups(int64_t rows, int K, int device_cus) {
-  (void)K;
-  int g = device_cus;  // one persistent group per compute unit
-  const int64_t min_groups = (rows + kMaxRowsW - 1) / kMaxRowsW;
-  const int64_t max_useful = (rows + 31) / 32;
-  if (g > max_useful) g = (int)max_useful;
-  if (g < min_groups) g = (int)min_groups;  // caller checks co-residency
-  if (g < 1) g = 1;
-  return g;
-}
-
-int hals_w_max_rows() { return kMaxRowsW; }
-
-// Largest cooperative grid of the W kernel for this slab height and K.
-int hals_w_max_coresident(int device_cus, int rows_per_group, int K) {
-  const size_t bytes = hals_smem_bytes(rows_per_group, K);
-  const void* fn = kernel_ptr<true, true>();
-  if (allow_smem(fn, bytes) != hipSuccess) return 0;
-  if (allow_smem(kernel_ptr<true, false>(), bytes) != hipSuccess) return 0;
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, hals_kernel<true, true>, 256, bytes) !=
-      hipSuccess)
-    return 0;
-  return nb * device_cus;
-}
-
-hipError_t hals_update(const HalsArgs& a, bool norm, int groups, hipStream_t s) {
+hipError_t hals_update(const HalsArgs& a, hipStream_t s) {
   const bool vec = (a.K % 4 == 0) && (((uintptr_t)a.X & 15) == 0);
-  if (!norm) {
-    HalsArgs b = a;
-    b.rows_per_group = kRowsH;
-    const unsigned grid = (unsigned)((a.rows + kRowsH - 1) / kRowsH);
-    if (grid == 0) return hipSuccess;
-    const size_t bytes = hals_smem_bytes(kRowsH, a.K);
-    const void* fn = vec ? kernel_ptr<false, true>() : kernel_ptr<false, false>();
-    hipError_t e = allow_smem(fn, bytes);
-    if (e != hipSuccess) return e;
-    if (vec) hals_kernel<false, true><<<grid, 256, bytes, s>>>(b);
-    else hals_kernel<false, false><<<grid, 256, bytes, s>>>(b);
-    return hipGetLastError();
-  }
-  HalsArgs b = a;
-  void* args[] = {&b};
-  const size_t bytes = hals_smem_bytes(a.rows_per_group, a.K);
-  const void* fn = vec ? kernel_ptr<true, true>() : kernel_ptr<true, false>();
+  const unsigned grid = (unsigned)((a.rows + kRowsH - 1) / kRowsH);
+  if (grid == 0) return hipSuccess;
+  const size_t bytes = h_smem_floats(a.K) * 4;
+  const void* fn = vec ? (const void*)hals_h_kernel<true> : (const void*)hals_h_kernel<false>;
   hipError_t e = allow_smem(fn, bytes);
   if (e != hipSuccess) return e;
-  return hipLaunchCooperativeKernel(fn, dim3(groups), dim3(256), args, (unsigned)bytes, s);
+  if (vec) hals_h_kernel<true><<<grid, 256, bytes, s>>>(a);
+  else hals_h_kernel<false><<<grid, 256, bytes, s>>>(a);
+  return hipGetLastError();
+}
+
+int hals_w_max_rows_per_group() { return kWMaxRows; }
+
+int hals_w_column_groups(int64_t rows) {
+  const int64_t n = (rows + kWMaxRows - 1) / kWMaxRows;
+  return n < 1 ? 1 : (int)n;
+}
+
+int hals_w_max_column_groups() { return kWMaxColGroups; }
+
+namespace {
+// Row blocks per product wave: column group g's blocks over its product groups.
+int jobs_per_wave(int rows_per_group, int grid, int n_col) {
+  const int min_npg = (grid - n_col) / n_col;
+  if (min_npg < 1) return 0;
+  const int nb = (rows_per_group + 31) / 32;
+  return (nb + kWWaves * min_npg - 1) / (kWWaves * min_npg);
+}
+}  // namespace
+
+int hals_w_rows_per_group(int64_t rows, int n_col) {
+  const int64_t r = (rows + n_col - 1) / n_col;
+  return (int)((r + 31) / 32 * 32);
+}
+
+int hals_w_grid(int device_cus, int64_t rows, int K, int n_col) {
+  const int grid = device_cus;  // one group per CU (the LDS request admits no second one)
+  if (n_col < 1 || 2 * n_col > grid || grid > kWFlagCol) return 0;
+  const int jpw = jobs_per_wave(hals_w_rows_per_group(rows, n_col), grid, n_col);
+  const size_t bytes = w_smem_bytes(K, jpw < 1 ? 1 : jpw);
+  if (jpw < 1 || bytes > kLdsMax) return 0;
+  for (int rpt : {1, 2, 4})
+    for (bool vec : {false, true})
+      for (bool local : {false, true}) {
+        const void* fn = w_kernel_for(rpt, vec, local);
+        if (allow_smem(fn, bytes) != hipSuccess) return 0;
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWThreads, bytes) != hipSuccess ||
+            nb < 1)
+          return 0;
+      }
+  return grid;
+}
+
+hipError_t hals_w_update(const HalsWArgs& a, int grid, hipStream_t s) {
+  if (a.rows <= 0 || a.K <= 0) return hipSuccess;
+  if (a.n_col < 1 || 2 * a.n_col > grid || a.n_col > kWMaxColGroups || a.rows_per_group > kWMaxRows ||
+      a.rows_per_group % 32 != 0 || (int64_t)a.n_col * a.rows_per_group < a.rows ||
+      grid > kWFlagCol)
+    return hipErrorInvalidValue;
+  HalsWArgs b = a;
+  b.jobs_per_wave = jobs_per_wave(a.rows_per_group, grid, a.n_col);
+  const size_t bytes = w_smem_bytes(a.K, b.jobs_per_wave);
+  if (b.jobs_per_wave < 1 || bytes > kLdsMax) return hipErrorInvalidValue;
+  const int rpt = (a.rows_per_group + kWRowThreads - 1) / kWRowThreads;
+  const bool vec = (a.K % 4 == 0) && (((uintptr_t)a.X & 15) == 0);
+  const void* fn = w_kernel_for(rpt, vec, a.n_col == 1);
+  hipError_t e = allow_smem(fn, bytes);
+  if (e != hipSuccess) return e;
+  void* args[] = {&b};
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kWThreads), args, (unsigned)bytes, s);
 }
 
 }  // namespace plnmf

@@ -121,7 +121,7 @@ hipError_t combine_objective(const double* a2, const double* wp, const double* s
 // --------------------------------------------------------- HALS updates ----
 // One tiled half-sweep over the rows of X [rows, K] (in place):
 //   acc[r,t] = Bterm[r,t] + X[r,t] * cdiag(t) - sum_{l != t} Xcur[r,l] G[l,t]
-//   X[r,t]   = max(eps, acc[r,t])       (NORM: then divided by the column norm)
+//   X[r,t]   = max(eps, acc[r,t])       (W half: then divided by the column norm)
 // cdiag = 1 - G[t,t] for the H update and 0 for the W update.
 struct HalsArgs {
   float* X;
@@ -130,18 +130,43 @@ struct HalsArgs {
   int64_t rows;
   int K;
   float eps;
-  int diag_one;          // 1: H update (cdiag = 1 - G_tt); 0: W update
-  int rows_per_group;    // slab height
-  unsigned long long* slots;  // NORM: [2][groups] tagged partials
-  unsigned epoch;
-  int32_t* status;       // bit 8 set on a wait timeout
+  int diag_one;          // 1: H update (cdiag = 1 - G_tt); 0: no diagonal term
 };
-hipError_t hals_update(const HalsArgs& a, bool norm, int groups, hipStream_t s);
-int hals_w_groups(int64_t rows, int K, int device_cus);
+// Row-independent update (no normalisation): the H half and fold-in.
+hipError_t hals_update(const HalsArgs& a, hipStream_t s);
 int hals_rows_per_group_h();
-int hals_w_max_coresident(int device_cus, int rows_per_group, int K);
-int hals_w_max_rows();
-size_t hals_smem_bytes(int rows_per_group, int K);
+
+constexpr int kWFlagCol = 1024;  // column-group flags follow the product-group flags
+constexpr int kWFlagWords = 2 * kWFlagCol;
+
+// The W half: column groups (phase 2, norm exchange) and product groups in one
+// cooperative launch of `grid` groups (see hals_w_grid).
+struct HalsWArgs {
+  float* X;                   // W [rows, K], in place
+  const float* Bterm;         // P [rows, K]
+  const float* G;             // Q [K, K]
+  int64_t rows;
+  int K;
+  float eps;
+  float* Y;                   // [ceil(K/32)][rows][32] hand-off: each tile's product
+  float* Wn;                  // [ceil(K/32)][rows][32] hand-off: each tile's new columns
+  unsigned long long* slots;  // kSlotWords tagged partials of the norm exchange
+  unsigned* flags;            // kWFlagWords tile flags (product, then column groups)
+  int n_col;                  // column groups, 1 <= n_col <= grid / 2
+  int rows_per_group;         // rows per column group (hals_w_rows_per_group)
+  unsigned epoch;             // distinct per launch (tags of slots and flags)
+  int32_t* status;            // bit 8 set on a wait timeout
+  int jobs_per_wave;          // set by hals_w_update
+};
+hipError_t hals_w_update(const HalsWArgs& a, int grid, hipStream_t s);
+int hals_w_max_rows_per_group();
+int hals_w_column_groups(int64_t rows);
+// Rows per column group for n_col groups: a multiple of 32.
+int hals_w_rows_per_group(int64_t rows, int n_col);
+int hals_w_max_column_groups();
+// Cooperative grid for this shape (one group per CU), or 0 if the kernel
+// cannot be made resident (LDS or occupancy).
+int hals_w_grid(int device_cus, int64_t rows, int K, int n_col);
 
 // ----------------------------------------------------------------- MLP ----
 hipError_t mlp_init_params(float* master, int64_t n, int K, int hidden, uint64_t seed,

@@ -94,6 +94,10 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
   double* red = c.take<double>((size_t)red_n);
   double* scal = c.take<double>(16);
   unsigned long long* slots = c.take<unsigned long long>(kSlotWords);
+  unsigned* wflags = c.take<unsigned>(kWFlagWords);
+  const int64_t wtiles = (K + kTile - 1) / kTile;
+  float* whand = c.take<float>((size_t)(wtiles * V * kTile));
+  float* wnew = c.take<float>((size_t)(wtiles * V * kTile));
   int32_t* status = c.take<int32_t>(16);
   double* colsq = c.take<double>((size_t)1024 * K);
   if (p) {
@@ -104,6 +108,9 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
     p->red_n = red_n;
     p->scal = scal;
     p->slots = slots;
+    p->w_flags = wflags;
+    p->w_handoff = whand;
+    p->w_new = wnew;
     p->status = status;
   }
   if (s.fmt == NMF_CSR) {
@@ -372,8 +379,7 @@ int half_h(nmf_plan_s* p) {
   a.K = p->K;
   a.eps = p->eps;
   a.diag_one = 1;
-  a.status = p->status;
-  TIMED(p, NMF_STEP_UPDATE_H, hals_update(a, false, 0, p->stream));
+  TIMED(p, NMF_STEP_UPDATE_H, hals_update(a, p->stream));
   p->pq_valid = false;
   return NMF_OK;
 }
@@ -381,19 +387,22 @@ int half_h(nmf_plan_s* p) {
 int half_w(nmf_plan_s* p) {
   TIMED(p, NMF_STEP_PRODUCT_P, product_P(p, false, p->P));
   TIMED(p, NMF_STEP_GRAM_Q, gram(p, p->Ht, p->D, p->Q));
-  HalsArgs a{};
+  HalsWArgs a{};
   a.X = p->W;
   a.Bterm = p->P;
   a.G = p->Q;
   a.rows = p->V;
   a.K = p->K;
   a.eps = p->eps;
-  a.diag_one = 0;
-  a.rows_per_group = p->w_rows_per_group;
+  a.Y = p->w_handoff;
+  a.Wn = p->w_new;
   a.slots = p->slots;
+  a.flags = p->w_flags;
+  a.n_col = p->w_groups;
+  a.rows_per_group = p->w_rows_per_group;
   a.epoch = next_epoch(p);
   a.status = p->status;
-  TIMED(p, NMF_STEP_UPDATE_W, hals_update(a, true, p->w_groups, p->stream));
+  TIMED(p, NMF_STEP_UPDATE_W, hals_w_update(a, p->w_grid, p->stream));
   p->pq_valid = p->prec == NMF_FP32;
   return NMF_OK;
 }
@@ -514,26 +523,30 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
     if (e_ != hipSuccess) return bail(fail(NMF_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_))); \
   } while (0)
 
-  // persistent W kernel grid: one group per CU unless overridden
-  int wg = hals_w_groups(s.V, K, cus);
-  if (const char* env = getenv("NMF_W_GROUPS")) {
-    int v = atoi(env);
-    if (v > 0) wg = std::min<int64_t>(v, (s.V + 31) / 32);
+  // W kernel: one cooperative group per CU; column groups of at most
+  // hals_w_max_rows_per_group() rows each (more, smaller ones on request)
+  int ncol = hals_w_column_groups(s.V);
+  if (const char* env = getenv("NMF_W_COLUMN_GROUPS")) {
+    const int v = atoi(env);
+    if (v > ncol) ncol = (int)std::min<int64_t>(std::min(v, hals_w_max_column_groups()), s.V);
   }
-  int64_t rpg = (s.V + wg - 1) / wg;
-  if (rpg > hals_w_max_rows())
-    return bail(fail(NMF_E_UNSUPPORTED, "V=%lld needs more than %d persistent groups",
-                     (long long)s.V, wg));
-  wg = (int)((s.V + rpg - 1) / rpg);
-  const int maxco = hals_w_max_coresident(cus, (int)rpg, K);
-  if (wg > maxco || wg > 1024)
-    return bail(fail(NMF_E_UNSUPPORTED, "W update needs %d co-resident groups, device allows %d", wg,
-                     maxco));
-  p->w_groups = wg;
+  const int64_t rpg = hals_w_rows_per_group(s.V, ncol);
+  ncol = (int)((s.V + rpg - 1) / rpg);
+  if (ncol > hals_w_max_column_groups())
+    return bail(fail(NMF_E_UNSUPPORTED, "V=%lld exceeds the W kernel's %d x %d rows",
+                     (long long)s.V, hals_w_max_column_groups(), hals_w_max_rows_per_group()));
+  const int grid = hals_w_grid(cus, s.V, K, ncol);
+  if (grid == 0)
+    return bail(fail(NMF_E_UNSUPPORTED,
+                     "the W kernel cannot be made resident for V=%lld, K=%d on %d CUs",
+                     (long long)s.V, K, cus));
+  p->w_grid = grid;
+  p->w_groups = ncol;
   p->w_rows_per_group = (int)rpg;
 
   INITCHECK(hipMemsetAsync(p->status, 0, 16 * sizeof(int32_t), st));
   INITCHECK(hipMemsetAsync(p->slots, 0, kSlotWords * sizeof(unsigned long long), st));
+  INITCHECK(hipMemsetAsync(p->w_flags, 0, kWFlagWords * sizeof(unsigned), st));
   // input checks: W, Ht finite and non-negative; A structure and values
   INITCHECK(check_finite_nonneg(W, s.V * K, p->status, 1, st));
   INITCHECK(check_finite_nonneg(Ht, s.D * K, p->status, 2, st));

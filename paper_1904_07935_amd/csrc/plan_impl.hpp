@@ -81,8 +81,12 @@ struct nmf_plan_s {
   int red_n = 0;
   double* scal = nullptr;   // [0] ||A||^2 [1] <W,P> [2] sum sq [3] half [4] rel
   unsigned long long* slots = nullptr;
+  unsigned* w_flags = nullptr;
+  float* w_handoff = nullptr;  // [ceil(K/kTile)][V][kTile] tile products
+  float* w_new = nullptr;      // [ceil(K/kTile)][V][kTile] finished tiles
   int32_t* status = nullptr;
-  int w_groups = 0;
+  int w_grid = 0;
+  int w_groups = 0;            // column groups of the W kernel
   int w_rows_per_group = 0;
   int tr_blocks = 1;
   unsigned epoch = 1;
