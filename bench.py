@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--profile-sweeps", type=int, default=5)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="afterwards, copy this many bytes device-to-device three times "
+                         "(a kernel of known traffic for scaling HBM counters)")
     return ap.parse_args()
 
 
@@ -112,7 +115,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "this build has no multi-GPU path", file=sys.stderr)
+              "the FAST-HALS library here runs on a single GPU", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -147,7 +150,7 @@ def main():
 
     # per-step event timing (separate pass; events on the plan's stream)
     plan.profile(True)
-    plan.sweep(args.profile_sweeps)
+    plan.sweep(max(args.profile_sweeps, 1))
     plan.profile(False)
     prof = plan.profile_read()
     per_step_us = {k: 1000.0 * v[0] / max(v[1], 1) for k, v in prof.items()}
@@ -186,6 +189,13 @@ def main():
         "w_groups": info["w_groups"],
         "rel_objective": rel,
     }
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_bytes"] = args.copy_bytes
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(corpus, W0, H0, args.cpu_sweeps)
     print(json.dumps(out))
