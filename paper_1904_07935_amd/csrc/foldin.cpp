@@ -24,6 +24,7 @@ struct FoldWs {
   float* S;       // [K,K]
   float* Qn;      // [K,K]
   float* partial;
+  float* gpart;   // Gram partials
   double* red;
   double* scal;   // [0] a2 [1] wp [2] sq [3] half [4] rel
   double* trace;  // [kTraceChunk]
@@ -49,15 +50,12 @@ FoldWs fold_layout(void* base, int64_t Dn, int64_t V, int K, const nmf_matrix* A
   f.Qn = c.take<float>((size_t)K * K);
   size_t part = 1;
   int64_t kps;
-  int sp = gemm_pick_splits(K, K, V, &kps);
-  if (sp > 1) part = std::max(part, (size_t)sp * K * K);
-  sp = gemm_pick_splits(K, K, Dn, &kps);
-  if (sp > 1) part = std::max(part, (size_t)sp * K * K);
   if (AnewT->format == NMF_DENSE) {
-    sp = gemm_pick_splits(Dn, K, V, &kps);
+    const int sp = gemm_pick_splits(Dn, K, V, &kps);
     if (sp > 1) part = std::max(part, (size_t)sp * Dn * K);
   }
   f.partial = c.take<float>(part);
+  f.gpart = c.take<float>(gram_partial_floats(K, gram_max_chunks()));
   f.red = c.take<double>(1024);
   f.scal = c.take<double>(8);
   f.trace = c.take<double>(kTraceChunk);
@@ -82,22 +80,9 @@ FoldWs fold_layout(void* base, int64_t Dn, int64_t V, int K, const nmf_matrix* A
   return f;
 }
 
-hipError_t gram_with(const float* X, int64_t rows, int K, float* out, float* partial, hipStream_t s) {
-  GemmArgs g{};
-  g.A = X;
-  g.B = X;
-  g.M = K;
-  g.N = K;
-  g.Kd = rows;
-  g.lda = K;
-  g.ldb = K;
-  g.C = out;
-  g.ldc = K;
-  g.epi = EPI_STORE;
-  g.splits = gemm_pick_splits(g.M, g.N, g.Kd, &g.k_per_split);
-  g.partial = partial;
-  g.sym = 1;
-  return gemm(Elem::F32, true, false, g, s);
+hipError_t gram_with(const float* X, int64_t rows, int K, float* out, float* gpart, int cus,
+                     hipStream_t s) {
+  return gram_xtx(X, rows, K, out, K, gpart, gram_chunks(rows, cus), s);
 }
 
 #define FCHECK(expr)                                                                      \
@@ -109,7 +94,7 @@ hipError_t gram_with(const float* X, int64_t rows, int K, float* out, float* par
 int fold_objective(nmf_plan_s* p, const FoldWs& f, float* Ht, int64_t Dn, double* dst,
                    hipStream_t s) {
   const int K = p->K;
-  FCHECK(gram_with(Ht, Dn, K, f.Qn, f.partial, s));
+  FCHECK(gram_with(Ht, Dn, K, f.Qn, f.gpart, p->cus, s));
   int nb = reduce_blocks(Dn * K);
   FCHECK(dot_f64(Ht, f.R, Dn * K, f.red, nb, s));
   FCHECK(finish_f64(f.red, nb, f.scal + 1, s));
@@ -210,7 +195,7 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
     FCHECK(sumsq_f64(AnewT->dense, Dn * p->V, f.red, nb, s));
     FCHECK(finish_f64(f.red, nb, f.scal + 0, s));
   }
-  FCHECK(gram_with(p->W, p->V, K, f.S, f.partial, s));
+  FCHECK(gram_with(p->W, p->V, K, f.S, f.gpart, p->cus, s));
 
   // initialisation of H for the new documents
   if (init_mode == NMF_FOLDIN_WTA) {

@@ -1,0 +1,201 @@
+// Gram matrices of the sweep, S = W^T W and Q = H H^T = Ht^T Ht (Alg. 1, the
+// S and Q statements): C = X^T X for X [rows, K] row-major, K <= 512.
+//
+// The contraction (rows) is long and the output small, so the work is split
+// by rows: one 512-thread workgroup per chunk of rows stages its chunk through
+// LDS (X is read from HBM exactly once) and accumulates the chunk's partial
+// Gram on the matrix cores, 32 x 32 output blocks of the upper triangle only
+// (C is symmetric), a fixed set of blocks per wave.  A second kernel adds the
+// chunks' partials in chunk order and writes both triangles: the result is
+// bitwise reproducible and independent of scheduling.
+#include "internal.hpp"
+
+namespace plnmf {
+namespace {
+
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
+constexpr int kRS = 32;             // rows per LDS stage
+constexpr int kMaxBlocksPerWave = 4;
+constexpr int kBlocksPerPass = kWaves * kMaxBlocksPerWave;
+
+__host__ __device__ inline int nblk(int K) { return (K + 31) / 32; }
+__host__ __device__ inline int upper_blocks(int K) { return nblk(K) * (nblk(K) + 1) / 2; }
+
+// block index u -> (bi, bj), bi <= bj, in row-major order of the upper triangle
+__device__ __forceinline__ void block_of(int u, int nb, int& bi, int& bj) {
+  int i = 0, rowlen = nb;
+  while (u >= rowlen) {
+    u -= rowlen;
+    i++;
+    rowlen--;
+  }
+  bi = i;
+  bj = i + u;
+}
+
+// partial[chunk][u][32][32] for the blocks u of pass blockIdx.y
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void gram_partial(const float* __restrict__ X, int64_t rows,
+                                                         int K, int64_t rows_per_chunk,
+                                                         float* __restrict__ partial) {
+  extern __shared__ float stage[];  // [kRS][P], P = 32 * nblk(K)
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int nb = nblk(K), P = 32 * nb, nu = upper_blocks(K);
+  const int64_t chunk = blockIdx.x;
+  const int64_t r0 = chunk * rows_per_chunk;
+  int64_t r1 = r0 + rows_per_chunk;
+  if (r1 > rows) r1 = rows;
+  const int ubase = blockIdx.y * kBlocksPerPass;
+  int bi[kMaxBlocksPerWave], bj[kMaxBlocksPerWave];
+  bool has[kMaxBlocksPerWave];
+#pragma unroll
+  for (int k = 0; k < kMaxBlocksPerWave; k++) {
+    const int u = ubase + k * kWaves + w;
+    has[k] = u < nu && u < ubase + kBlocksPerPass;
+    if (has[k]) block_of(u, nb, bi[k], bj[k]);
+    else bi[k] = bj[k] = 0;
+  }
+  floatx16 acc[kMaxBlocksPerWave];
+#pragma unroll
+  for (int k = 0; k < kMaxBlocksPerWave; k++)
+#pragma unroll
+    for (int e = 0; e < 16; e++) acc[k][e] = 0.0f;
+
+  const int nq = P / 4;  // float4 per staged row
+  for (int64_t s0 = r0; s0 < r1; s0 += kRS) {
+    __syncthreads();  // the previous stage is no longer read
+    for (int i = tid; i < kRS * nq; i += kThreads) {
+      const int rl = i / nq, q = i % nq;
+      const int64_t r = s0 + rl;
+      const int c = 4 * q;
+      floatx4 v = floatx4{0, 0, 0, 0};
+      if (r < r1) {
+        const float* src = X + r * K + c;
+        if constexpr (VEC) {
+          if (c < K) v = *(const floatx4*)src;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; e++)
+            if (c + e < K) v[e] = src[e];
+        }
+      }
+      *(floatx4*)(stage + rl * P + c) = v;
+    }
+    __syncthreads();
+    const int h = lane >> 5, m = lane & 31;
+#pragma unroll 4
+    for (int kk = 0; kk < kRS; kk += 2) {
+      const float* row = stage + (kk + h) * P;
+#pragma unroll
+      for (int k = 0; k < kMaxBlocksPerWave; k++)
+        if (has[k])
+          acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(row[32 * bi[k] + m], row[32 * bj[k] + m],
+                                                         acc[k], 0, 0, 0);
+    }
+  }
+  // lane holds C block row 8 j + 4 h + i, column lane % 32, in acc[4 j + i]
+  const int h = lane >> 5, n = lane & 31;
+#pragma unroll
+  for (int k = 0; k < kMaxBlocksPerWave; k++) {
+    if (!has[k]) continue;
+    const int u = ubase + k * kWaves + w;
+    float* dst = partial + ((int64_t)chunk * nu + u) * 1024;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) dst[(8 * j + 4 * h + i) * 32 + n] = acc[k][4 * j + i];
+  }
+}
+
+// C[K][K] from the partials: workgroup (u, part) handles 32 float4 of block u;
+// thread (f, sl) sums chunks sl, sl + 32, ... of float4 f, then slice 0 adds
+// the 32 slice sums in slice order.
+constexpr int kRedSlices = 32;
+
+__global__ __launch_bounds__(1024) void gram_reduce(const float* __restrict__ partial, int nchunks,
+                                                    int K, float* __restrict__ C, int64_t ldc) {
+  __shared__ floatx4 part[1024];
+  const int nb = nblk(K), nu = upper_blocks(K);
+  const int u = blockIdx.x / 8, piece = blockIdx.x % 8;
+  const int t = threadIdx.x, f = piece * 32 + (t & 31), sl = t >> 5;
+  floatx4 acc = floatx4{0, 0, 0, 0};
+  int c = sl;
+  for (; c + 3 * kRedSlices < nchunks; c += 4 * kRedSlices) {
+    const floatx4 a0 = *(const floatx4*)(partial + ((int64_t)c * nu + u) * 1024 + 4 * f);
+    const floatx4 a1 = *(const floatx4*)(partial + ((int64_t)(c + kRedSlices) * nu + u) * 1024 + 4 * f);
+    const floatx4 a2 = *(const floatx4*)(partial + ((int64_t)(c + 2 * kRedSlices) * nu + u) * 1024 + 4 * f);
+    const floatx4 a3 = *(const floatx4*)(partial + ((int64_t)(c + 3 * kRedSlices) * nu + u) * 1024 + 4 * f);
+    acc += a0;
+    acc += a1;
+    acc += a2;
+    acc += a3;
+  }
+  for (; c < nchunks; c += kRedSlices)
+    acc += *(const floatx4*)(partial + ((int64_t)c * nu + u) * 1024 + 4 * f);
+  part[t] = acc;
+  __syncthreads();
+  if (sl == 0) {
+    floatx4 tot = part[t];
+    for (int k = 1; k < kRedSlices; k++) tot += part[k * 32 + (t & 31)];
+    int bi, bj;
+    {
+      int uu = u, i = 0, rowlen = nb;
+      while (uu >= rowlen) {
+        uu -= rowlen;
+        i++;
+        rowlen--;
+      }
+      bi = i;
+      bj = i + uu;
+    }
+    const int rr = (4 * f) / 32, cc = (4 * f) % 32;  // element (rr, cc..cc+3) of the block
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int gi = 32 * bi + rr, gj = 32 * bj + cc + e;
+      if (gi < K && gj < K) {
+        C[(int64_t)gi * ldc + gj] = tot[e];
+        if (bi != bj) C[(int64_t)gj * ldc + gi] = tot[e];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+constexpr int kMaxChunks = 256;
+
+int gram_max_chunks() { return kMaxChunks; }
+
+int gram_chunks(int64_t rows, int device_cus) {
+  int64_t n = (rows + 63) / 64;
+  if (n > device_cus) n = device_cus;
+  if (n > kMaxChunks) n = kMaxChunks;
+  return n < 1 ? 1 : (int)n;
+}
+
+size_t gram_partial_floats(int K, int chunks) { return (size_t)chunks * upper_blocks(K) * 1024; }
+
+hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, float* partial,
+                    int chunks, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  if (K > kMaxK || chunks < 1) return hipErrorInvalidValue;
+  const int64_t rpc = (rows + chunks - 1) / chunks;
+  const int passes = (upper_blocks(K) + kBlocksPerPass - 1) / kBlocksPerPass;
+  const size_t bytes = (size_t)kRS * 32 * nblk(K) * 4;
+  const bool vec = (K % 4 == 0) && (((uintptr_t)X & 15) == 0);
+  const void* fn = vec ? (const void*)gram_partial<true> : (const void*)gram_partial<false>;
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  const dim3 grid((unsigned)chunks, (unsigned)passes);
+  if (vec) gram_partial<true><<<grid, kThreads, bytes, s>>>(X, rows, K, rpc, partial);
+  else gram_partial<false><<<grid, kThreads, bytes, s>>>(X, rows, K, rpc, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  gram_reduce<<<(unsigned)(upper_blocks(K) * 8), 1024, 0, s>>>(partial, chunks, K, C, ldc);
+  return hipGetLastError();
+}
+
+}  // namespace plnmf

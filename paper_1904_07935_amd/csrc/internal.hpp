@@ -60,6 +60,14 @@ int gemm_pick_splits(int64_t M, int64_t N, int64_t Kd, int64_t* k_per_split);
 hipError_t splitk_reduce(const float* partial, int splits, int64_t M, int64_t N, float* C,
                          int64_t ldc, const float* bias, int sym, hipStream_t s);
 
+// ------------------------------------------------------------------ Gram ----
+// C[K][K] (ldc) = X^T X for X [rows, K] row-major, K <= kMaxK; deterministic.
+int gram_chunks(int64_t rows, int device_cus);  // <= gram_max_chunks()
+int gram_max_chunks();
+size_t gram_partial_floats(int K, int chunks);
+hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, float* partial,
+                    int chunks, hipStream_t s);
+
 // ------------------------------------------------------------------ SpMM ----
 // out[r, 0:K] = sum_j val[j] X[col[j], 0:K] over the rows of a CSR matrix.
 // Work items (one wave each), planned on the host by spmm_build: runs of short

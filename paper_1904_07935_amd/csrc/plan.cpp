@@ -82,13 +82,12 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
     int sp = gemm_pick_splits(M, N, Kd, &kps);
     if (sp > 1) part = std::max(part, (size_t)(sp * M * N));
   };
-  need(K, K, V);
-  need(K, K, D);
   if (s.fmt == NMF_DENSE) {
     need(D, K, V);
     need(V, K, D);
   }
   float* partial = c.take<float>(std::max<size_t>(part, 1));
+  float* gpart = c.take<float>(gram_partial_floats((int)K, gram_max_chunks()));
   const int64_t resid_tiles = ((V + 127) / 128) * ((D + 127) / 128);
   const int red_n = (int)std::max<int64_t>(std::max<int64_t>(resid_tiles, 1024), 1);
   double* red = c.take<double>((size_t)red_n);
@@ -103,6 +102,7 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
   if (p) {
     p->colsq = colsq;
     p->partial = partial;
+    p->gram_part = gpart;
     p->partial_floats = std::max<size_t>(part, 1);
     p->red = red;
     p->red_n = red_n;
@@ -228,21 +228,7 @@ int plnmf::device_check(int* dev, int* cus) {
 
 // ------------------------------------------------------- step launchers ----
 hipError_t plnmf::gram(nmf_plan_s* p, const float* X, int64_t rows, float* out) {
-  GemmArgs g{};
-  g.A = X;
-  g.B = X;
-  g.M = p->K;
-  g.N = p->K;
-  g.Kd = rows;
-  g.lda = p->K;
-  g.ldb = p->K;
-  g.C = out;
-  g.ldc = p->K;
-  g.epi = EPI_STORE;
-  g.splits = gemm_pick_splits(g.M, g.N, g.Kd, &g.k_per_split);
-  g.partial = p->partial;
-  g.sym = 1;
-  return gemm(Elem::F32, true, false, g, p->stream);
+  return gram_xtx(X, rows, p->K, out, p->K, p->gram_part, gram_chunks(rows, p->cus), p->stream);
 }
 
 namespace {

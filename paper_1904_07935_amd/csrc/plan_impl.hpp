@@ -75,6 +75,7 @@ struct nmf_plan_s {
   float* S2 = nullptr;
   float* P2 = nullptr;      // FP32 A H^T for the objective of BF16 plans
   float* partial = nullptr;
+  float* gram_part = nullptr;   // per-chunk partial Grams
   size_t partial_floats = 0;
   double* colsq = nullptr;
   double* red = nullptr;

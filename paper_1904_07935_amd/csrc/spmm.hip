@@ -123,18 +123,58 @@ __global__ __launch_bounds__(256) void spmm_items(SpmmKArgs a) {
   }
 }
 
-// One wave per long row: add its segments' partial rows in segment order.
-__global__ __launch_bounds__(256) void spmm_fixup(const int32_t* __restrict__ fix, int64_t n_fix,
-                                                  const float* __restrict__ carry,
-                                                  float* __restrict__ out, int K) {
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+// One workgroup per long row: add its segments' partial rows.  Thread (v, sl)
+// sums columns 4v..4v+3 over segments sl, sl + S, ... (S slices, in order, four
+// loads in flight), then slice 0 adds the S slice sums in slice order: a fixed
+// order for a given K and segment count, so results are bitwise reproducible.
+constexpr int kFixThreads = 512;
+
+__global__ __launch_bounds__(kFixThreads) void spmm_fixup(const int32_t* __restrict__ fix,
+                                                          int64_t n_fix,
+                                                          const float* __restrict__ carry,
+                                                          float* __restrict__ out, int K) {
+  __shared__ floatx4 part[kFixThreads];
+  const int64_t i = blockIdx.x;
   if (i >= n_fix) return;
-  const int lane = threadIdx.x & 63;
+  const int nv = (K + 3) / 4;
+  const int S = kFixThreads / nv > 0 ? kFixThreads / nv : 1;
+  const int t = threadIdx.x;
+  const int v = t % nv, sl = t / nv;
   const int64_t r = fix[3 * i], first = fix[3 * i + 1], cnt = fix[3 * i + 2];
-  for (int k = lane; k < K; k += 64) {
-    float s = 0.0f;
-    for (int64_t g = 0; g < cnt; g++) s += carry[(first + g) * K + k];
-    out[r * K + k] = s;
+  const bool vec = (K % 4) == 0;
+  floatx4 acc = floatx4{0, 0, 0, 0};
+  if (sl < S && t < nv * S) {
+    auto seg = [&](int64_t g) -> floatx4 {
+      const float* p = carry + (first + g) * K + 4 * v;
+      if (vec) return *(const floatx4*)p;
+      floatx4 x;
+#pragma unroll
+      for (int e = 0; e < 4; e++) x[e] = 4 * v + e < K ? p[e] : 0.0f;
+      return x;
+    };
+    int64_t g = sl;
+    for (; g + 3 * S < cnt; g += 4 * S) {
+      const floatx4 x0 = seg(g), x1 = seg(g + S), x2 = seg(g + 2 * S), x3 = seg(g + 3 * S);
+      acc += x0;
+      acc += x1;
+      acc += x2;
+      acc += x3;
+    }
+    for (; g < cnt; g += S) acc += seg(g);
+  }
+  part[t] = acc;
+  __syncthreads();
+  if (sl == 0 && t < nv) {
+    floatx4 tot = part[v];
+    for (int k = 1; k < S; k++) tot += part[k * nv + v];
+    float* dst = out + r * K + 4 * v;
+    if (vec) {
+      *(floatx4*)dst = tot;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        if (4 * v + e < K) dst[e] = tot[e];
+    }
   }
 }
 
@@ -252,7 +292,7 @@ hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hip
                                 : launch_k<__bf16, __bf16>(a, vec, s);
   if (e != hipSuccess) return e;
   if (p.n_fix > 0) {
-    spmm_fixup<<<(unsigned)((p.n_fix + 3) / 4), 256, 0, s>>>(p.fix, p.n_fix, p.carry, out, K);
+    spmm_fixup<<<(unsigned)p.n_fix, kFixThreads, 0, s>>>(p.fix, p.n_fix, p.carry, out, K);
     e = hipGetLastError();
   }
   return e;
