@@ -25,6 +25,7 @@ struct FoldWs {
   float* Qn;      // [K,K]
   float* partial;
   float* gpart;   // Gram partials
+  float* panel;   // tile panels of the H update
   double* red;
   double* scal;   // [0] a2 [1] wp [2] sq [3] half [4] rel
   double* trace;  // [kTraceChunk]
@@ -56,6 +57,7 @@ FoldWs fold_layout(void* base, int64_t Dn, int64_t V, int K, const nmf_matrix* A
   }
   f.partial = c.take<float>(part);
   f.gpart = c.take<float>(gram_partial_floats(K, gram_max_chunks()));
+  f.panel = c.take<float>(hals_panel_floats(K));
   f.red = c.take<double>(1024);
   f.scal = c.take<double>(8);
   f.trace = c.take<double>(kTraceChunk);
@@ -81,8 +83,8 @@ FoldWs fold_layout(void* base, int64_t Dn, int64_t V, int K, const nmf_matrix* A
 }
 
 hipError_t gram_with(const float* X, int64_t rows, int K, float* out, float* gpart, int cus,
-                     hipStream_t s) {
-  return gram_xtx(X, rows, K, out, K, gpart, gram_chunks(rows, cus), s);
+                     hipStream_t s, float* panel = nullptr) {
+  return gram_xtx(X, rows, K, out, K, gpart, gram_chunks(rows, cus), s, panel, 1);
 }
 
 #define FCHECK(expr)                                                                      \
@@ -195,7 +197,8 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
     FCHECK(sumsq_f64(AnewT->dense, Dn * p->V, f.red, nb, s));
     FCHECK(finish_f64(f.red, nb, f.scal + 0, s));
   }
-  FCHECK(gram_with(p->W, p->V, K, f.S, f.gpart, p->cus, s));
+  FCHECK(hipMemsetAsync(f.panel, 0, hals_panel_floats(K) * sizeof(float), s));
+  FCHECK(gram_with(p->W, p->V, K, f.S, f.gpart, p->cus, s, f.panel));
 
   // initialisation of H for the new documents
   if (init_mode == NMF_FOLDIN_WTA) {
@@ -215,6 +218,7 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
   a.K = K;
   a.eps = p->eps;
   a.diag_one = 1;
+  a.panel = f.panel;
   int filled = 0;  // trace entries waiting in f.trace
   int written = 0; // trace entries copied to the host
   auto flush = [&]() -> int {

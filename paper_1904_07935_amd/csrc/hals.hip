@@ -29,8 +29,8 @@
 // W half: each column needs the L2 norm of the finished column over all rows
 // before the next column can be clipped (Alg. 1 normalises inside the k
 // loop), so phase 2 is a chain of K chip-level reductions and their latency,
-// not arithmetic, bounds the kernel.  One cooperative launch of one 512-thread
-// workgroup per CU splits the work by role:
+// not arithmetic, bounds the kernel.  One launch of one 512-thread workgroup
+// per CU (all resident at once) splits the work by role:
 //   * column groups (few, about 2048 rows each) hold the tile's 32 columns of
 //     their rows in registers and run phase 2, exchanging one FP32 partial per
 //     column through tagged 64-bit slots.  They are the workgroups whose index
@@ -46,6 +46,8 @@
 // tagged flags over device-scope (XCD-coherent) loads and stores.  All waits are
 // bounded: on a timeout a status bit is set, every group stops waiting, and
 // the kernel still runs to completion.
+#include <cstdlib>
+
 #include "internal.hpp"
 
 namespace plnmf {
@@ -263,155 +265,162 @@ __device__ __forceinline__ floatx16 block_product(const float* __restrict__ xr, 
   return acc;
 }
 
-// Staging of the tile's G block gt [T][TP] and of the product's B panel
-// bp [kpad(K)][TP] (bm_value) by NT threads, eight loads in flight per thread.
-constexpr int kStageU = 8;
-
-template <int NT>
-__device__ __forceinline__ void stage_gt(const float* __restrict__ G, int K, int a0, int tw, float* gt) {
-  const int tid = threadIdx.x;
-  for (int i0 = 0; i0 < T * T; i0 += NT * kStageU) {
-    float v[kStageU];
-#pragma unroll
-    for (int u = 0; u < kStageU; u++) {
-      const int i = i0 + tid + NT * u, r = i / T, c = i % T;
-      v[u] = (i < T * T && r < tw && c < tw) ? G[(int64_t)(a0 + r) * K + a0 + c] : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < kStageU; u++) {
-      const int i = i0 + tid + NT * u;
-      if (i < T * T) gt[(i / T) * TP + i % T] = v[u];
-    }
-  }
-}
-
-template <int NT>
-__device__ __forceinline__ void stage_bp(const float* __restrict__ G, int K, int a0, int b0,
-                                         int diag_one, float* bp) {
-  const int tid = threadIdx.x;
-  const int n = kpad(K) * T;
-  for (int i0 = 0; i0 < n; i0 += NT * kStageU) {
-    float v[kStageU];
-#pragma unroll
-    for (int u = 0; u < kStageU; u++) {
-      const int i = i0 + tid + NT * u;
-      v[u] = i < n ? bm_value(G, K, i / T, a0 + i % T, a0, b0, diag_one) : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < kStageU; u++) {
-      const int i = i0 + tid + NT * u;
-      if (i < n) bp[(i / T) * TP + i % T] = v[u];
-    }
-  }
-}
-
 // ---------------------------------------------------------------- H half ----
 
-// dynamic LDS (floats): xt [32][TP] | gt [T][TP] | part [4][32][TP] | bp [Kp][TP],
-// Kp = K rounded up to a multiple of 8 (rows >= K of bp hold zeros)
+// One workgroup per 32 rows, the whole sweep of Alg. 1's H loop for them.  The
+// rows live in LDS from start to end (updated in place); per tile: the tile
+// product on the matrix cores with the contraction split over the four waves,
+// Bterm added, then phase 2 by wave 0 (one lane per row, the tile's columns in
+// registers) while waves 1..3 stage the next tile's panel.
+// LDS (floats): xs [32][XP] | bp [kpad(K)][TP] | gt [2][T][TP] | part [3][32][TP],
+// XP = 32 * ntiles + 1 (odd: conflict-free row and column access).
+__host__ __device__ inline int h_xp(int K) { return 32 * ((K + T - 1) / T) + 1; }
 __host__ __device__ inline size_t h_smem_floats(int K) {
-  return (size_t)kRowsH * TP + (size_t)T * TP + 4 * 32 * TP + (size_t)kpad(K) * TP;
+  return (size_t)kRowsH * h_xp(K) + (size_t)kpad(K) * TP + 2 * T * TP + 3 * 32 * TP;
 }
 
-// The tile product of this group's rows into xt (Bterm added).  With fewer
-// than four 32-row blocks the contraction is split over the idle waves.
-template <bool VEC>
-__device__ void h_tile_product(const HalsArgs& a, float* xt, float* part, const float* bp,
-                               int64_t row0, int64_t row1, int nr, int a0, int tw) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int K = a.K;
-  const int nrb = (nr + 31) / 32;
-  const int parts = nrb >= 4 ? 1 : (nrb == 2 ? 2 : (nrb == 1 ? 4 : 1));
-  const int chunk = ((K + parts - 1) / parts + 7) / 8 * 8;  // multiple of 8: MFMA k-groups
-  const int h = lane >> 5;
-  for (int job = w; job < nrb * parts; job += 4) {
-    const int rb = job / parts, p = job % parts;
-    const int lb = p * chunk;
-    const int le = lb + chunk < K ? lb + chunk : K;
-    const int64_t r = row0 + rb * 32 + (lane & 31);
-    const bool rok = r < row1;
-    const floatx16 acc = block_product<VEC>(a.X + (rok ? r : row0) * K, rok, lb, le, bp, lane);
-    if (parts == 1) {
-#pragma unroll
-      for (int j = 0; j < 4; j++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const int rl = rb * 32 + 8 * j + 4 * h + i;
-          const int cl = lane & 31;
-          if (rl < nr && cl < tw) xt[rl * TP + cl] = acc[4 * j + i] + a.Bterm[(row0 + rl) * K + a0 + cl];
-        }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; j++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) part[(w * 32 + 8 * j + 4 * h + i) * TP + (lane & 31)] = acc[4 * j + i];
-    }
+__device__ __forceinline__ void copy_panel(const float* __restrict__ panel, const float* __restrict__ gblk,
+                                           int K, int j, float* bp, float* gt, int t0, int nt) {
+  const int kp = kpad(K);
+  const floatx4* src = (const floatx4*)(panel + (int64_t)j * kp * T);
+  for (int i = t0; i < kp * T / 4; i += nt) {
+    const floatx4 v = src[i];
+    float* d = bp + (4 * i / T) * TP + (4 * i) % T;
+    d[0] = v[0];
+    d[1] = v[1];
+    d[2] = v[2];
+    d[3] = v[3];
   }
-  if (parts > 1) {
-    __syncthreads();
-    for (int i = tid; i < nr * tw; i += 256) {
-      const int rl = i / tw, cl = i % tw;
-      const int rb = rl / 32;
-      float v = a.Bterm[(row0 + rl) * K + a0 + cl];
-      for (int p = 0; p < parts; p++) v += part[((rb * parts + p) * 32 + rl % 32) * TP + cl];
-      xt[rl * TP + cl] = v;
-    }
+  const floatx4* gs = (const floatx4*)(gblk + (int64_t)j * T * T);
+  for (int i = t0; i < T * T / 4; i += nt) {
+    const floatx4 v = gs[i];
+    float* d = gt + (4 * i / T) * TP + (4 * i) % T;
+    d[0] = v[0];
+    d[1] = v[1];
+    d[2] = v[2];
+    d[3] = v[3];
   }
 }
 
 template <bool VEC>
 __global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
   extern __shared__ float smem_raw[];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int K = a.K;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, m = lane & 31;
+  const int K = a.K, kp = kpad(K), XP = h_xp(K), ntiles = (K + T - 1) / T;
   const int64_t row0 = (int64_t)blockIdx.x * kRowsH;
-  int64_t row1 = row0 + kRowsH;
-  if (row1 > a.rows) row1 = a.rows;
-  const int nr = row0 < row1 ? (int)(row1 - row0) : 0;
-  float* xt = smem_raw;
-  float* gt = xt + kRowsH * TP;
-  float* part = gt + T * TP;
-  float* bp = part + 4 * 32 * TP;
-  float* __restrict__ X = a.X;
+  const int nr = a.rows - row0 < kRowsH ? (int)(a.rows - row0) : kRowsH;
+  float* xs = smem_raw;
+  float* bp = xs + kRowsH * XP;
+  float* gtb = bp + kp * TP;
+  float* part = gtb + 2 * T * TP;
   const float eps = a.eps;
 
-  for (int a0 = 0; a0 < K; a0 += T) {
-    const int b0 = a0 + T < K ? a0 + T : K;
-    const int tw = b0 - a0;
-    stage_gt<256>(a.G, K, a0, tw, gt);
-    stage_bp<256>(a.G, K, a0, b0, a.diag_one, bp);
-    __syncthreads();
-    h_tile_product<VEC>(a, xt, part, bp, row0, row1, nr, a0, tw);
-    __syncthreads();
+  // the group's rows, zero-padded to 32 * ntiles columns
+  const int nq = 8 * ntiles;
+  for (int i = tid; i < kRowsH * nq; i += 256) {
+    const int rl = i / nq, c = 4 * (i % nq);
+    floatx4 v = floatx4{0, 0, 0, 0};
+    if (rl < nr) {
+      const float* src = a.X + (row0 + rl) * K + c;
+      if constexpr (VEC) {
+        if (c < K) v = *(const floatx4*)src;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+          if (c + e < K) v[e] = src[e];
+      }
+    }
+    float* d = xs + rl * XP + c;
+    d[0] = v[0];
+    d[1] = v[1];
+    d[2] = v[2];
+    d[3] = v[3];
+  }
+  copy_panel(a.panel, a.gblk, K, 0, bp, gtb, tid, 256);
+  __syncthreads();
 
-    // phase 2: one thread per row with the tile's 32 columns in registers
-    if (tid < kRowsH) {
-      const int rl = tid;
-      const bool rok = rl < nr;
-      float y[T];
+  const int chunk = ((kp + 3) / 4 + 7) / 8 * 8;  // contraction per wave, a multiple of 8
+  const int lb = w * chunk, le = lb + chunk < kp ? lb + chunk : kp;
+  for (int j = 0; j < ntiles; j++) {
+    const int a0 = j * T, tw = a0 + T < K ? T : K - a0;
+    const float* gt = gtb + (j & 1) * T * TP;
+    // wave 0: this tile's Bterm in the product's lane layout
+    float bt[16];
+    if (w == 0) {
 #pragma unroll
-      for (int c = 0; c < T; c++) y[c] = rok ? xt[rl * TP + c] : 0.0f;
+      for (int jj = 0; jj < 4; jj++)
 #pragma unroll
-      for (int t = 0; t < T; t++) {
-        if (t < tw) {
-          const float x = fmaxf(eps, y[t]);
-          y[t] = x;
-#pragma unroll
-          for (int c = t + 1; c < T; c++) y[c] -= x * gt[t * TP + c];
+        for (int i = 0; i < 4; i++) {
+          const int rl = 8 * jj + 4 * h + i;
+          bt[4 * jj + i] = (rl < nr && m < tw) ? a.Bterm[(row0 + rl) * K + a0 + m] : 0.0f;
         }
-      }
-      if (rok) {
+    }
+    // the tile product, contraction [lb, le) of this wave
+    floatx16 acc;
 #pragma unroll
-        for (int c = 0; c < T; c++) xt[rl * TP + c] = y[c];
+    for (int e = 0; e < 16; e++) acc[e] = 0.0f;
+    for (int l = lb; l < le; l += 8) {
+#pragma unroll
+      for (int s = 0; s < 4; s++) {
+        const int ll = l + 2 * s + h;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[m * XP + ll], bp[ll * TP + m], acc, 0, 0, 0);
       }
     }
-    __syncthreads();
-    // write the finished tile back (rows are K-contiguous)
-    for (int i = tid; i < nr * tw; i += 256) {
-      const int rl = i / tw, cl = i % tw;
-      X[(row0 + rl) * K + a0 + cl] = xt[rl * TP + cl];
+    if (w > 0) {
+      float* pw = part + (w - 1) * 32 * TP;
+#pragma unroll
+      for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) pw[(8 * jj + 4 * h + i) * TP + m] = acc[4 * jj + i];
     }
     __syncthreads();
+    if (w == 0) {
+      // y = Bterm + product, into part[0] (each element read, then written, by one lane)
+#pragma unroll
+      for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int e = (8 * jj + 4 * h + i) * TP + m;
+          part[e] = bt[4 * jj + i] + ((acc[4 * jj + i] + part[e]) + part[32 * TP + e]) + part[64 * TP + e];
+        }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      // phase 2: one lane per row, the tile's columns in registers
+      if (lane < kRowsH) {
+        float y[T];
+#pragma unroll
+        for (int c = 0; c < T; c++) y[c] = part[lane * TP + c];
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+          if (t < tw) {
+            const float x = fmaxf(eps, y[t]);
+            y[t] = x;
+#pragma unroll
+            for (int c = t + 1; c < T; c++) y[c] -= x * gt[t * TP + c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < T; c++)
+          if (c < tw) xs[lane * XP + a0 + c] = y[c];
+      }
+    } else if (j + 1 < ntiles) {
+      // waves 1..3: the next tile's panel (bp is free once every wave has its product)
+      copy_panel(a.panel, a.gblk, K, j + 1, bp, gtb + ((j + 1) & 1) * T * TP, tid - 64, 192);
+    }
+    __syncthreads();
+  }
+  // the finished rows back to X
+  for (int i = tid; i < kRowsH * nq; i += 256) {
+    const int rl = i / nq, c = 4 * (i % nq);
+    if (rl >= nr || c >= K) continue;
+    const float* sp = xs + rl * XP + c;
+    float* dst = a.X + (row0 + rl) * K + c;
+    if constexpr (VEC) {
+      *(floatx4*)dst = floatx4{sp[0], sp[1], sp[2], sp[3]};
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        if (c + e < K) dst[e] = sp[e];
+    }
   }
 }
 
@@ -504,7 +513,18 @@ __device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n
   for (int j = 0, a0 = 0; a0 < K; j++, a0 += T) {
     const int tw = a0 + T < K ? T : K - a0;
     __syncthreads();  // gt of the previous tile is no longer read
-    stage_gt<kWThreads>(a.G, K, a0, tw, gt);
+    {
+      const floatx4* src =
+          (const floatx4*)(a.panel + (int64_t)((K + T - 1) / T) * kpad(K) * T + (int64_t)j * T * T);
+      for (int i = tid; i < T * T / 4; i += kWThreads) {
+        const floatx4 v = src[i];
+        float* d = gt + (4 * i / T) * TP + (4 * i) % T;
+        d[0] = v[0];
+        d[1] = v[1];
+        d[2] = v[2];
+        d[3] = v[3];
+      }
+    }
     // the product groups serving this column group: rank, rank + n_col, ...
     await_flags(a.flags + rank, (n_prod - rank + a.n_col - 1) / a.n_col, a.n_col,
                 tile_tag(a.epoch, j), a.status);
@@ -706,7 +726,17 @@ __device__ __forceinline__ void w_product_role(const HalsWArgs a, int prank, int
     const int b0 = a0 + T < K ? a0 + T : K;
     const int tw = b0 - a0;
     __syncthreads();  // the previous tile's products no longer read bp
-    stage_bp<kWThreads>(a.G, K, a0, b0, 0, bp);
+    {
+      const floatx4* src = (const floatx4*)(a.panel + (int64_t)j * kpad(K) * T);
+      for (int i = tid; i < kpad(K) * T / 4; i += kWThreads) {
+        const floatx4 v = src[i];
+        float* d = bp + (4 * i / T) * TP + (4 * i) % T;
+        d[0] = v[0];
+        d[1] = v[1];
+        d[2] = v[2];
+        d[3] = v[3];
+      }
+    }
     __syncthreads();
     // before the wait: Bterm plus every segment but the previous tile's
     for (int k = 0; k < jpw; k++) {
@@ -807,16 +837,24 @@ hipError_t allow_smem(const void* fn, size_t bytes) {
 
 int hals_rows_per_group_h() { return kRowsH; }
 
+size_t hals_panel_floats(int K) {
+  const int ntiles = (K + T - 1) / T;
+  return (size_t)ntiles * kpad(K) * T + (size_t)ntiles * T * T;
+}
+
 hipError_t hals_update(const HalsArgs& a, hipStream_t s) {
-  const bool vec = (a.K % 4 == 0) && (((uintptr_t)a.X & 15) == 0);
   const unsigned grid = (unsigned)((a.rows + kRowsH - 1) / kRowsH);
-  if (grid == 0) return hipSuccess;
+  if (grid == 0 || a.K <= 0) return hipSuccess;
+  if (a.K > kMaxK || !a.panel) return hipErrorInvalidValue;
+  HalsArgs b = a;
+  b.gblk = a.panel + (int64_t)((a.K + T - 1) / T) * kpad(a.K) * T;
+  const bool vec = (a.K % 4 == 0) && (((uintptr_t)a.X & 15) == 0);
   const size_t bytes = h_smem_floats(a.K) * 4;
   const void* fn = vec ? (const void*)hals_h_kernel<true> : (const void*)hals_h_kernel<false>;
   hipError_t e = allow_smem(fn, bytes);
   if (e != hipSuccess) return e;
-  if (vec) hals_h_kernel<true><<<grid, 256, bytes, s>>>(a);
-  else hals_h_kernel<false><<<grid, 256, bytes, s>>>(a);
+  if (vec) hals_h_kernel<true><<<grid, 256, bytes, s>>>(b);
+  else hals_h_kernel<false><<<grid, 256, bytes, s>>>(b);
   return hipGetLastError();
 }
 
@@ -869,6 +907,7 @@ hipError_t hals_w_update(const HalsWArgs& a, int grid, hipStream_t s) {
       a.rows_per_group % 32 != 0 || (int64_t)a.n_col * a.rows_per_group < a.rows ||
       grid > kWFlagCol)
     return hipErrorInvalidValue;
+  if (!a.panel) return hipErrorInvalidValue;
   HalsWArgs b = a;
   b.jobs_per_wave = jobs_per_wave(a.rows_per_group, grid, a.n_col);
   const size_t bytes = w_smem_bytes(a.K, b.jobs_per_wave);
@@ -879,7 +918,19 @@ hipError_t hals_w_update(const HalsWArgs& a, int grid, hipStream_t s) {
   hipError_t e = allow_smem(fn, bytes);
   if (e != hipSuccess) return e;
   void* args[] = {&b};
-  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kWThreads), args, (unsigned)bytes, s);
+  // One group per CU, checked resident at plan creation (hals_w_grid), on a
+  // stream whose earlier kernels have finished: a plain launch makes every
+  // group resident.  The cooperative API guarantees it even on a shared device
+  // but costs ~25 us per launch here; NMF_W_COOPERATIVE=1 selects it.  Without
+  // it, a group that cannot become resident ends the sweep with a timeout
+  // error (bounded waits), never a hang.
+  static const bool coop = [] {
+    const char* e = getenv("NMF_W_COOPERATIVE");
+    return e && atoi(e) > 0;
+  }();
+  if (coop)
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kWThreads), args, (unsigned)bytes, s);
+  return hipLaunchKernel(fn, dim3(grid), dim3(kWThreads), args, bytes, s);
 }
 
 }  // namespace plnmf

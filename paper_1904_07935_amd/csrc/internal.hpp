@@ -65,8 +65,11 @@ hipError_t splitk_reduce(const float* partial, int splits, int64_t M, int64_t N,
 int gram_chunks(int64_t rows, int device_cus);  // <= gram_max_chunks()
 int gram_max_chunks();
 size_t gram_partial_floats(int K, int chunks);
+// With `panel` set, also writes the tile panels of the column updates derived
+// from C (hals_panel_floats(K) floats; entries that never depend on C -- rows
+// >= K, and outside the last tile -- must have been zeroed once).
 hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, float* partial,
-                    int chunks, hipStream_t s);
+                    int chunks, hipStream_t s, float* panel = nullptr, int diag_one = 0);
 
 // ------------------------------------------------------------------ SpMM ----
 // out[r, 0:K] = sum_j val[j] X[col[j], 0:K] over the rows of a CSR matrix.
@@ -139,9 +142,12 @@ struct HalsArgs {
   int K;
   float eps;
   int diag_one;          // 1: H update (cdiag = 1 - G_tt); 0: no diagonal term
+  const float* panel;    // tile panels of G (gram_xtx with panel output, diag_one as here)
+  const float* gblk;     // set by hals_update
 };
 // Row-independent update (no normalisation): the H half and fold-in.
 hipError_t hals_update(const HalsArgs& a, hipStream_t s);
+size_t hals_panel_floats(int K);
 int hals_rows_per_group_h();
 
 constexpr int kWFlagCol = 1024;  // column-group flags follow the product-group flags
@@ -164,6 +170,7 @@ struct HalsWArgs {
   int rows_per_group;         // rows per column group (hals_w_rows_per_group)
   unsigned epoch;             // distinct per launch (tags of slots and flags)
   int32_t* status;            // bit 8 set on a wait timeout
+  const float* panel;         // tile panels of Q (gram_xtx with panel output, diag_one 0)
   int jobs_per_wave;          // set by hals_w_update
 };
 hipError_t hals_w_update(const HalsWArgs& a, int grid, hipStream_t s);

@@ -88,6 +88,7 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
   }
   float* partial = c.take<float>(std::max<size_t>(part, 1));
   float* gpart = c.take<float>(gram_partial_floats((int)K, gram_max_chunks()));
+  float* panel = c.take<float>(hals_panel_floats((int)K));
   const int64_t resid_tiles = ((V + 127) / 128) * ((D + 127) / 128);
   const int red_n = (int)std::max<int64_t>(std::max<int64_t>(resid_tiles, 1024), 1);
   double* red = c.take<double>((size_t)red_n);
@@ -103,6 +104,7 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
     p->colsq = colsq;
     p->partial = partial;
     p->gram_part = gpart;
+    p->panel = panel;
     p->partial_floats = std::max<size_t>(part, 1);
     p->red = red;
     p->red_n = red_n;
@@ -227,8 +229,9 @@ int plnmf::device_check(int* dev, int* cus) {
 }
 
 // ------------------------------------------------------- step launchers ----
-hipError_t plnmf::gram(nmf_plan_s* p, const float* X, int64_t rows, float* out) {
-  return gram_xtx(X, rows, p->K, out, p->K, p->gram_part, gram_chunks(rows, p->cus), p->stream);
+hipError_t plnmf::gram(nmf_plan_s* p, const float* X, int64_t rows, float* out, int panel_diag) {
+  return gram_xtx(X, rows, p->K, out, p->K, p->gram_part, gram_chunks(rows, p->cus), p->stream,
+                  panel_diag >= 0 ? p->panel : nullptr, panel_diag);
 }
 
 namespace {
@@ -355,7 +358,7 @@ void prof_clear(nmf_plan_s* p) {
 }
 
 int half_h(nmf_plan_s* p) {
-  TIMED(p, NMF_STEP_GRAM_S, gram(p, p->W, p->V, p->S));
+  TIMED(p, NMF_STEP_GRAM_S, gram(p, p->W, p->V, p->S, 1));  // + the H update's panels
   TIMED(p, NMF_STEP_PRODUCT_R, product_R(p));
   HalsArgs a{};
   a.X = p->Ht;
@@ -365,6 +368,7 @@ int half_h(nmf_plan_s* p) {
   a.K = p->K;
   a.eps = p->eps;
   a.diag_one = 1;
+  a.panel = p->panel;
   TIMED(p, NMF_STEP_UPDATE_H, hals_update(a, p->stream));
   p->pq_valid = false;
   return NMF_OK;
@@ -372,7 +376,7 @@ int half_h(nmf_plan_s* p) {
 
 int half_w(nmf_plan_s* p) {
   TIMED(p, NMF_STEP_PRODUCT_P, product_P(p, false, p->P));
-  TIMED(p, NMF_STEP_GRAM_Q, gram(p, p->Ht, p->D, p->Q));
+  TIMED(p, NMF_STEP_GRAM_Q, gram(p, p->Ht, p->D, p->Q, 0));  // + the W update's panels
   HalsWArgs a{};
   a.X = p->W;
   a.Bterm = p->P;
@@ -382,6 +386,7 @@ int half_w(nmf_plan_s* p) {
   a.eps = p->eps;
   a.Y = p->w_handoff;
   a.Wn = p->w_new;
+  a.panel = p->panel;
   a.slots = p->slots;
   a.flags = p->w_flags;
   a.n_col = p->w_groups;
@@ -533,6 +538,7 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
   INITCHECK(hipMemsetAsync(p->status, 0, 16 * sizeof(int32_t), st));
   INITCHECK(hipMemsetAsync(p->slots, 0, kSlotWords * sizeof(unsigned long long), st));
   INITCHECK(hipMemsetAsync(p->w_flags, 0, kWFlagWords * sizeof(unsigned), st));
+  INITCHECK(hipMemsetAsync(p->panel, 0, hals_panel_floats(K) * sizeof(float), st));
   // input checks: W, Ht finite and non-negative; A structure and values
   INITCHECK(check_finite_nonneg(W, s.V * K, p->status, 1, st));
   INITCHECK(check_finite_nonneg(Ht, s.D * K, p->status, 2, st));

@@ -76,6 +76,7 @@ struct nmf_plan_s {
   float* P2 = nullptr;      // FP32 A H^T for the objective of BF16 plans
   float* partial = nullptr;
   float* gram_part = nullptr;   // per-chunk partial Grams
+  float* panel = nullptr;       // precomputed tile panels of the H update
   size_t partial_floats = 0;
   double* colsq = nullptr;
   double* red = nullptr;
@@ -99,6 +100,8 @@ struct nmf_plan_s {
 };
 
 namespace plnmf {
-hipError_t gram(nmf_plan_s* p, const float* X, int64_t rows, float* out);
+// out = X^T X; with panel_diag >= 0 also the column updates' tile panels
+// (p->panel) with that diagonal rule
+hipError_t gram(nmf_plan_s* p, const float* X, int64_t rows, float* out, int panel_diag = -1);
 int enqueue_objective(nmf_plan_s* p);
 }  // namespace plnmf
