@@ -434,14 +434,15 @@ constexpr int kWMaxRows = kWRowThreads * kWMaxRpt;  // rows per column group
 constexpr size_t kWSmemMin = 82 * 1024;             // > half the LDS: one group per CU
 constexpr int kWMaxColGroups = 64;
 
-// LDS (floats).  Column role: gt [T][TP] | wave slots [2][kWWaves] | total slots [2] (u64) |
-// lane partials [2][kWWaves - 1][64].  Product role: bp [kpad(K)][TP] | per-wave
-// stash [kWWaves][jobs per wave][32][TP] (partial products, then the transpose).
+// LDS (floats).  Column role: gt [T][TP] | wave slots [2][kWWaves] | total slots [2] |
+// protocol flag [2] (u64) | lane partials [2][kWWaves - 1][64].  Product role:
+// bp [kpad(K)][TP] | per-wave stash [kWWaves][jobs per wave][32][TP] (partial
+// products, then the transpose).
 constexpr size_t kLdsMax = 160 * 1024;
 
 __host__ __device__ inline size_t w_smem_bytes(int K, int jpw) {
   size_t b = ((size_t)kpad(K) * TP + (size_t)kWWaves * jpw * 32 * TP) * 4;
-  const size_t col = (size_t)T * TP * 4 + (2 * kWWaves + 2) * 8 + 2 * (kWWaves - 1) * 64 * 4;
+  const size_t col = (size_t)T * TP * 4 + (2 * kWWaves + 4) * 8 + 2 * (kWWaves - 1) * 64 * 4;
   if (b < col) b = col;
   return b < kWSmemMin ? kWSmemMin : b;
 }
@@ -477,23 +478,73 @@ __device__ __forceinline__ void lds_post(unsigned long long* slot, unsigned tag,
   __hip_atomic_store(slot, pack_slot(tag, v), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Column groups.  Waves 1..7 hold rows (RPT per thread) and run phase 2; wave
-// 0 runs the column-norm exchange: it sums the row waves' partials (tagged LDS
-// slots, wave order), publishes the group's partial, sums all groups'
-// partials and posts the total back in LDS.  No workgroup barrier separates
-// two columns, and the exchange wave starts polling as soon as it has
-// published, while the row waves apply the previous column to the rest of
-// the tile.  LOCAL: a single column group, no exchange between groups.
-template <int RPT, bool VEC, bool LOCAL>
-__device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n_prod, float* lds) {
+// Column groups.  Waves 1..7 hold rows (RPT per thread) and run phase 2: per
+// column, each posts its partial sum of u_t^2, applies the previous column to
+// the rest of the tile while the exchange is in flight, and then needs the sum
+// of all partials.  Three exchange protocols, all summing in a fixed order (so
+// every wave of every group gets the bitwise-identical norm):
+//  * LOCAL (one column group): partials in tagged LDS slots, every row wave
+//    sums the seven of them.
+//  * XCD: all column groups run on one XCD (checked at kernel start): every
+//    row wave publishes its partial with a non-temporal store and sums all
+//    partials of all groups with non-temporal loads -- both served by that
+//    XCD's L2, which all its CUs share (about half the latency of device-scope
+//    accesses, which go past the L2; measured).
+//  * DEVICE (any placement): wave 0 sums the row waves' lane partials from LDS,
+//    exchanges one partial per group through device-scope slots and posts the
+//    total back in LDS.
+// No workgroup barrier separates two columns.  Tags and values share one 64-bit
+// word, so a slot is either this column's value or not yet ready.
+enum : int { kProtoLocal = 0, kProtoXcd = 1, kProtoDevice = 2 };
+constexpr int kSlotDev = 0;      // [2][n_col] group partials (device scope)
+constexpr int kSlotPlace = 256;  // [n_col] XCD of each column group (device scope)
+constexpr int kSlotXcd = 512;    // [2][7 n_col] row-wave partials (XCD-local)
+constexpr int kXcdMaxParts = 256;
+static_assert(kSlotXcd + 2 * kXcdMaxParts <= kSlotWords, "slot regions");
+static_assert(kWMaxColGroups <= 256 - kSlotDev / 2, "slot regions");
+
+__device__ __forceinline__ float collect_xcd(const unsigned long long* base, int n, unsigned tag,
+                                             int32_t* status) {
+  constexpr int MAXS = kXcdMaxParts / 64;
+  const int lane = threadIdx.x & 63;
+  unsigned long long v[MAXS];
+#pragma unroll
+  for (int s = 0; s < MAXS; s++) v[s] = 0;  // tags are never 0 (epoch >= 1)
+  int spins = 0;
+  bool done;
+  do {
+    asm volatile("" ::: "memory");  // reload every round
+    bool mine = true;
+#pragma unroll
+    for (int s = 0; s < MAXS; s++) {
+      const int i = lane + 64 * s;
+      if (i < n && (unsigned)(v[s] >> 32) != tag) {
+        v[s] = __builtin_nontemporal_load(base + i);
+        mine = mine && (unsigned)(v[s] >> 32) == tag;
+      }
+    }
+    done = __all(mine);
+    if (!done && (++spins & 255) == 0 && timed_out(status)) break;
+  } while (!done && spins < kSpinLimit);
+  if (!done && lane == 0) atomicOr(status, 256);
+  float t = 0.0f;
+#pragma unroll
+  for (int s = 0; s < MAXS; s++)
+    if (lane + 64 * s < n) t += __uint_as_float((unsigned)v[s]);
+  return wave_sum(t);
+}
+
+template <int RPT, bool VEC, int PROTO>
+__device__ __forceinline__ void column_tiles(const HalsWArgs& a, int rank, int n_prod, float* lds) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const bool xwave = w == 0;
   const int K = a.K;
   const int64_t rows = a.rows;
+  const int nparts = a.n_col * (kWWaves - 1);
   float* gt = lds;  // [T][TP] G of the tile
   unsigned long long* lpart = (unsigned long long*)(lds + T * TP);  // [2][kWWaves]
   unsigned long long* ltot = lpart + 2 * kWWaves;                   // [2]
-  float* lvals = (float*)(ltot + 2);                                // [2][kWWaves - 1][64]
+  float* lvals = (float*)(ltot + 4);                                // [2][kWWaves - 1][64]
   const int64_t row0 = (int64_t)rank * a.rows_per_group;
   int64_t row1 = row0 + a.rows_per_group;
   if (row1 > rows) row1 = rows;
@@ -508,7 +559,6 @@ __device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n
     valid[q] = !xwave && rr[q] < row1;
   }
   float y[RPT][T];
-  if (tid < 2 * kWWaves + 2) lpart[tid] = 0;  // no stale tags (the first barrier below orders it)
 
   for (int j = 0, a0 = 0; a0 < K; j++, a0 += T) {
     const int tw = a0 + T < K ? T : K - a0;
@@ -529,21 +579,20 @@ __device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n
     await_flags(a.flags + rank, (n_prod - rank + a.n_col - 1) / a.n_col, a.n_col,
                 tile_tag(a.epoch, j), a.status);
     if (xwave) {
-      for (int t = 0; t < tw; t++) {
-        const unsigned ctag = (a.epoch << 10) | (unsigned)(a0 + t);
-        const int par = (a0 + t) & 1;
-        if (lane >= 1 && lane < kWWaves) lds_wait(lpart + par * kWWaves + lane, ctag, a.status);
-        // the group's partial: per lane over the row waves in order, then across lanes
-        float g = 0.0f;
+      if constexpr (PROTO == kProtoDevice) {
+        for (int t = 0; t < tw; t++) {
+          const unsigned ctag = (a.epoch << 10) | (unsigned)(a0 + t);
+          const int par = (a0 + t) & 1;
+          if (lane >= 1 && lane < kWWaves) lds_wait(lpart + par * kWWaves + lane, ctag, a.status);
+          // the group's partial: per lane over the row waves in order, then across lanes
+          float g = 0.0f;
 #pragma unroll
-        for (int i = 0; i < kWWaves - 1; i++) g += lvals[(par * (kWWaves - 1) + i) * 64 + lane];
-        g = wave_sum(g);
-        float tot = g;
-        if constexpr (!LOCAL) {
-          if (lane < kSlotReplicas) publish(a.slots, a.n_col, rank, ctag, par, g, lane);
-          tot = collect_sum64(a.slots, a.n_col, rank, ctag, par, a.status);
+          for (int i = 0; i < kWWaves - 1; i++) g += lvals[(par * (kWWaves - 1) + i) * 64 + lane];
+          g = wave_sum(g);
+          if (lane < kSlotReplicas) publish(a.slots + kSlotDev, a.n_col, rank, ctag, par, g, lane);
+          const float tot = collect_sum64(a.slots + kSlotDev, a.n_col, rank, ctag, par, a.status);
+          if (lane == 0) lds_post(ltot + par, ctag, tot);
         }
-        if (lane == 0) lds_post(ltot + par, ctag, tot);
       }
     } else {
       // this group's rows of the tile's product (one contiguous run of rows per wave)
@@ -573,8 +622,19 @@ __device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n
         if (t < tw) {
           const unsigned ctag = (a.epoch << 10) | (unsigned)(a0 + t);
           const int par = (a0 + t) & 1;
-          lvals[(par * (kWWaves - 1) + (w - 1)) * 64 + lane] = ss;
-          if (lane == 0) lds_post(lpart + par * kWWaves + w, ctag, 0.0f);
+          if constexpr (PROTO == kProtoDevice) {
+            lvals[(par * (kWWaves - 1) + (w - 1)) * 64 + lane] = ss;
+            if (lane == 0) lds_post(lpart + par * kWWaves + w, ctag, 0.0f);
+          } else if constexpr (PROTO == kProtoXcd) {
+            const float mine = wave_sum(ss);
+            if (lane == 0)
+              __builtin_nontemporal_store(
+                  pack_slot(ctag, mine),
+                  a.slots + kSlotXcd + par * nparts + rank * (kWWaves - 1) + (w - 1));
+          } else {
+            const float mine = wave_sum(ss);
+            if (lane == 0) lds_post(lpart + par * kWWaves + w, ctag, mine);
+          }
           // off the critical path: the previous column's contribution to columns > t
           if (t > 0) {
 #pragma unroll
@@ -585,7 +645,19 @@ __device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n
             }
           }
           const float gnext = t + 1 < T ? gt[t * TP + t + 1] : 0.0f;
-          const float tot = lds_wait(ltot + par, ctag, a.status);
+          float tot;
+          if constexpr (PROTO == kProtoDevice) {
+            tot = lds_wait(ltot + par, ctag, a.status);
+          } else if constexpr (PROTO == kProtoXcd) {
+            tot = collect_xcd(a.slots + kSlotXcd + par * nparts, nparts, ctag, a.status);
+          } else {
+            float part = 0.0f;
+            if (lane >= 1 && lane < kWWaves) part = lds_wait(lpart + par * kWWaves + lane, ctag, a.status);
+            tot = 0.0f;
+#pragma unroll
+            for (int i = 1; i < kWWaves; i++)
+              tot += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, part), i));
+          }
           const float rn = 1.0f / sqrtf(tot);
           ss = 0.0f;
 #pragma unroll
@@ -613,6 +685,44 @@ __device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n
       }
     }
     signal_flag(a.flags + kWFlagCol + rank, tile_tag(a.epoch, j));
+  }
+}
+
+template <int RPT, bool VEC, bool LOCAL>
+__device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n_prod, float* lds) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  unsigned long long* lpart = (unsigned long long*)(lds + T * TP);
+  int* lflag = (int*)(lpart + 2 * kWWaves + 2);
+  if (tid < 2 * kWWaves + 2) lpart[tid] = 0;  // no stale tags (the barrier below orders it)
+  if constexpr (LOCAL) {
+    __syncthreads();
+    column_tiles<RPT, VEC, kProtoLocal>(a, rank, n_prod, lds);
+  } else {
+    // are all column groups on one XCD?  (one device-scope exchange per launch;
+    // every group sees the same answers, so all take the same protocol)
+    if (tid < 64) {
+      const unsigned xcc = __builtin_amdgcn_s_getreg((31 << 11) | (0 << 6) | 20);
+      const unsigned ptag = (a.epoch << 10) | 1023u;  // no column has index 1023
+      if (lane == 0)
+        __hip_atomic_store(a.slots + kSlotPlace + rank, pack_slot(ptag, __uint_as_float(xcc)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned long long v = (unsigned long long)ptag << 32;
+      int spins = 0;
+      bool done;
+      do {
+        if (lane < a.n_col)
+          v = __hip_atomic_load(a.slots + kSlotPlace + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        done = __all((unsigned)(v >> 32) == ptag);
+        if (!done && (++spins & 255) == 0 && timed_out(a.status)) break;
+      } while (!done && spins < kSpinLimit);
+      if (!done && lane == 0) atomicOr(a.status, 256);
+      const unsigned first = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 0);
+      const bool same = __all(lane >= a.n_col || (unsigned)v == first);
+      if (lane == 0) *lflag = same && a.n_col * (kWWaves - 1) <= kXcdMaxParts;
+    }
+    __syncthreads();
+    if (*lflag) column_tiles<RPT, VEC, kProtoXcd>(a, rank, n_prod, lds);
+    else column_tiles<RPT, VEC, kProtoDevice>(a, rank, n_prod, lds);
   }
 }
 

@@ -15,7 +15,7 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxK = 512;
 constexpr int kTile = 32;          // tile width T of the column-update kernels
 constexpr int kSpinLimit = 1 << 21; // bounded waits: a few seconds of polling at most
-constexpr int kSlotReplicas = 8;    // copies of the column-norm exchange slots
+constexpr int kSlotReplicas = 1;    // copies of the column-norm exchange slots
 constexpr int kSlotStride = 2 * 1024 + 16;  // u64 elements between replicas
 constexpr int kSlotWords = kSlotReplicas * kSlotStride;
 

@@ -99,6 +99,24 @@ def test_w_column_groups_match_oracle(cuda, monkeypatch, groups):
     plan.close()
 
 
+def test_w_column_groups_across_xcds_match_oracle(cuda, monkeypatch):
+    """Enough column groups that they cannot share one XCD: the W half takes
+    the device-scope exchange instead of the XCD-local one; results stay within
+    the bars of the oracle."""
+    c = small_bow()
+    K = 24
+    W0, H0 = sparse_init(c, K)
+    monkeypatch.setenv("NMF_W_COLUMN_GROUPS", "60")
+    plan = gpu_plan(c.A, W0, H0, cuda)
+    assert plan.info()["w_groups"] > 36
+    rel_gpu = np.array(plan.sweep(10, objective=True))
+    rel_or, facs = oracle_run(c.A, W0, H0, 10)
+    assert np.max(np.abs(rel_gpu - rel_or) / rel_or) <= 1e-5
+    assert rel_fro(_np(plan.W), facs[-1][0]) <= 1e-3
+    np.testing.assert_allclose(np.linalg.norm(_np(plan.W), axis=0), 1.0, rtol=1e-5)
+    plan.close()
+
+
 @pytest.mark.parametrize("K", [5, 24, 64])
 def test_sparse_parity(cuda, K):
     c = small_bow()
