@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kThreads) void gram_partial(const float* __restrict
     const int u = ubase + k * kWaves + w;
     has[k] = u < nu && u < ubase + kBlocksPerPass;
     if (has[k]) block_of(u, nb, bi[k], bj[k]);
-    else bi[k] = bj[k] = 0;
+    else bi[k] = bj[k] = 0;  // computed like block (0, 0), never stored: no branch in the loop
   }
   floatx16 acc[kMaxBlocksPerWave];
 #pragma unroll
@@ -63,14 +63,16 @@ __global__ __launch_bounds__(kThreads) void gram_partial(const float* __restrict
     for (int e = 0; e < 16; e++) acc[k][e] = 0.0f;
 
   const int nq = P / 4;  // float4 per staged row
-  for (int64_t s0 = r0; s0 < r1; s0 += kRS) {
-    __syncthreads();  // the previous stage is no longer read
-    for (int i = tid; i < kRS * nq; i += kThreads) {
-      const int rl = i / nq, q = i % nq;
+  // thread's share of a stage: float4 i = tid + kThreads * u of kRS * nq
+  constexpr int kPer = (kRS * 32 * kMaxK / 32 / 4 + kThreads - 1) / kThreads;  // <= 8
+  auto fetch = [&](int64_t s0, floatx4 (&buf)[kPer]) {
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      const int i = tid + kThreads * u;
+      const int rl = i / nq, c = 4 * (i % nq);
       const int64_t r = s0 + rl;
-      const int c = 4 * q;
       floatx4 v = floatx4{0, 0, 0, 0};
-      if (r < r1) {
+      if (i < kRS * nq && r < r1) {
         const float* src = X + r * K + c;
         if constexpr (VEC) {
           if (c < K) v = *(const floatx4*)src;
@@ -80,22 +82,40 @@ __global__ __launch_bounds__(kThreads) void gram_partial(const float* __restrict
             if (c + e < K) v[e] = src[e];
         }
       }
-      *(floatx4*)(stage + rl * P + c) = v;
+      buf[u] = v;
     }
+  };
+  auto put = [&](const floatx4 (&buf)[kPer]) {
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      const int i = tid + kThreads * u;
+      if (i < kRS * nq) *(floatx4*)(stage + (i / nq) * P + 4 * (i % nq)) = buf[u];
+    }
+  };
+  floatx4 nxt[kPer];
+  fetch(r0, nxt);
+  const int h = lane >> 5, m = lane & 31;
+  for (int64_t s0 = r0; s0 < r1; s0 += kRS) {
+    __syncthreads();  // the previous stage is no longer read
+    put(nxt);
     __syncthreads();
-    const int h = lane >> 5, m = lane & 31;
-#pragma unroll 4
+    if (s0 + kRS < r1) fetch(s0 + kRS, nxt);  // in flight during this stage's products
+#pragma unroll
     for (int kk = 0; kk < kRS; kk += 2) {
       const float* row = stage + (kk + h) * P;
+      float av[kMaxBlocksPerWave], bv[kMaxBlocksPerWave];
+#pragma unroll
+      for (int k = 0; k < kMaxBlocksPerWave; k++) {
+        av[k] = row[32 * bi[k] + m];
+        bv[k] = row[32 * bj[k] + m];
+      }
 #pragma unroll
       for (int k = 0; k < kMaxBlocksPerWave; k++)
-        if (has[k])
-          acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(row[32 * bi[k] + m], row[32 * bj[k] + m],
-                                                         acc[k], 0, 0, 0);
+        acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k], bv[k], acc[k], 0, 0, 0);
     }
   }
   // lane holds C block row 8 j + 4 h + i, column lane % 32, in acc[4 j + i]
-  const int h = lane >> 5, n = lane & 31;
+  const int n = lane & 31;
 #pragma unroll
   for (int k = 0; k < kMaxBlocksPerWave; k++) {
     if (!has[k]) continue;
@@ -109,9 +129,10 @@ __global__ __launch_bounds__(kThreads) void gram_partial(const float* __restrict
 }
 
 // C[K][K] from the partials: workgroup (u, part) handles 32 float4 of block u;
-// thread (f, sl) sums chunks sl, sl + 32, ... of float4 f, then slice 0 adds
-// the 32 slice sums in slice order.
-constexpr int kRedSlices = 32;
+// thread (f, sl) sums chunks sl, sl + 16, ... of float4 f, then slice 0 adds
+// the 16 slice sums in slice order.
+constexpr int kRedSlices = 16;
+constexpr int kRedThreads = 32 * kRedSlices;
 
 // Panel entry of C[l][col] for the tile products of the column updates (the B
 // operand of the tile of col, contraction row l): 1 - C or 0 on the diagonal,
@@ -128,10 +149,10 @@ __device__ __forceinline__ void put_panel(float* panel, int K, int diag_one, int
   if (l / 32 == j) panel[(int64_t)ntiles * kp * 32 + ((int64_t)j * 32 + (l - a0)) * 32 + c] = v;
 }
 
-__global__ __launch_bounds__(1024) void gram_reduce(const float* __restrict__ partial, int nchunks,
+__global__ __launch_bounds__(kRedThreads) void gram_reduce(const float* __restrict__ partial, int nchunks,
                                                     int K, float* __restrict__ C, int64_t ldc,
                                                     float* __restrict__ panel, int diag_one) {
-  __shared__ floatx4 part[1024];
+  __shared__ floatx4 part[kRedThreads];
   const int nb = nblk(K), nu = upper_blocks(K);
   const int u = blockIdx.x / 8, piece = blockIdx.x % 8;
   const int t = threadIdx.x, f = piece * 32 + (t & 31), sl = t >> 5;
@@ -214,7 +235,7 @@ hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, 
   else gram_partial<false><<<grid, kThreads, bytes, s>>>(X, rows, K, rpc, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  gram_reduce<<<(unsigned)(upper_blocks(K) * 8), 1024, 0, s>>>(partial, chunks, K, C, ldc, panel,
+  gram_reduce<<<(unsigned)(upper_blocks(K) * 8), kRedThreads, 0, s>>>(partial, chunks, K, C, ldc, panel,
                                                                 diag_one);
   return hipGetLastError();
 }
