@@ -507,6 +507,7 @@ __device__ __forceinline__ float collect_xcd(const unsigned long long* base, int
                                              int32_t* status) {
   constexpr int MAXS = kXcdMaxParts / 64;
   const int lane = threadIdx.x & 63;
+  const int ns = (n + 63) / 64;  // uniform: slot rows in use
   unsigned long long v[MAXS];
 #pragma unroll
   for (int s = 0; s < MAXS; s++) v[s] = 0;  // tags are never 0 (epoch >= 1)
@@ -514,15 +515,18 @@ __device__ __forceinline__ float collect_xcd(const unsigned long long* base, int
   bool done;
   do {
     asm volatile("" ::: "memory");  // reload every round
+    // every row's load in flight at once (lanes past n re-read slot n - 1),
+    // then one wait: a round costs one L2 round trip, not one per row
+#pragma unroll
+    for (int s = 0; s < MAXS; s++)
+      if (s < ns) {
+        const int i = lane + 64 * s;
+        v[s] = __builtin_nontemporal_load(base + (i < n ? i : n - 1));
+      }
     bool mine = true;
 #pragma unroll
-    for (int s = 0; s < MAXS; s++) {
-      const int i = lane + 64 * s;
-      if (i < n && (unsigned)(v[s] >> 32) != tag) {
-        v[s] = __builtin_nontemporal_load(base + i);
-        mine = mine && (unsigned)(v[s] >> 32) == tag;
-      }
-    }
+    for (int s = 0; s < MAXS; s++)
+      if (s < ns) mine = mine && (lane + 64 * s >= n || (unsigned)(v[s] >> 32) == tag);
     done = __all(mine);
     if (!done && (++spins & 255) == 0 && timed_out(status)) break;
   } while (!done && spins < kSpinLimit);
@@ -643,6 +647,12 @@ __device__ __forceinline__ void column_tiles(const HalsWArgs& a, int rank, int n
 #pragma unroll
               for (int q = 0; q < RPT; q++) y[q][c] -= xprev[q] * gv;
             }
+            // finished here, before the wait: left to itself the compiler sinks
+            // these products below the polling loop, onto the critical path
+#pragma unroll
+            for (int c = t + 1; c < T; c++)
+#pragma unroll
+              for (int q = 0; q < RPT; q++) asm volatile("" : "+v"(y[q][c]));
           }
           const float gnext = t + 1 < T ? gt[t * TP + t + 1] : 0.0f;
           float tot;
@@ -970,9 +980,17 @@ hipError_t hals_update(const HalsArgs& a, hipStream_t s) {
 
 int hals_w_max_rows_per_group() { return kWMaxRows; }
 
-int hals_w_column_groups(int64_t rows) {
-  const int64_t n = (rows + kWMaxRows - 1) / kWMaxRows;
-  return n < 1 ? 1 : (int)n;
+int hals_w_column_groups(int64_t rows, int device_cus) {
+  const int64_t need = (rows + kWMaxRows - 1) / kWMaxRows;
+  if (need <= 1) return 1;  // one group: the exchange stays in LDS
+  // otherwise as many groups as one XCD holds (down to one row per row thread):
+  // fewer rows per group shorten the per-column arithmetic and the per-tile
+  // hand-offs, and the exchange among the groups of one XCD costs about the same
+  int64_t n = (rows + kWRowThreads - 1) / kWRowThreads;
+  const int64_t xcd = device_cus / 8;
+  if (n > xcd) n = xcd;
+  if (n < need) n = need;
+  return (int)n;
 }
 
 int hals_w_max_column_groups() { return kWMaxColGroups; }

@@ -175,7 +175,7 @@ struct HalsWArgs {
 };
 hipError_t hals_w_update(const HalsWArgs& a, int grid, hipStream_t s);
 int hals_w_max_rows_per_group();
-int hals_w_column_groups(int64_t rows);
+int hals_w_column_groups(int64_t rows, int device_cus);
 // Rows per column group for n_col groups: a multiple of 32.
 int hals_w_rows_per_group(int64_t rows, int n_col);
 int hals_w_max_column_groups();

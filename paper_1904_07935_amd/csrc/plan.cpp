@@ -514,9 +514,9 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
     if (e_ != hipSuccess) return bail(fail(NMF_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_))); \
   } while (0)
 
-  // W kernel: one cooperative group per CU; column groups of at most
+  // W kernel: one group per CU; column groups of at most
   // hals_w_max_rows_per_group() rows each (more, smaller ones on request)
-  int ncol = hals_w_column_groups(s.V);
+  int ncol = hals_w_column_groups(s.V, cus);
   if (const char* env = getenv("NMF_W_COLUMN_GROUPS")) {
     const int v = atoi(env);
     if (v > ncol) ncol = (int)std::min<int64_t>(std::min(v, hals_w_max_column_groups()), s.V);
