@@ -13,6 +13,16 @@
 // leave partial rows that a second pass adds up in segment order; nothing
 // else needs a second pass, and no atomics are used: results are
 // bitwise-reproducible.
+//
+// Wide rows (K > 128: one nonzero per wave step) take a flat variant.  A wave
+// walking an item row by row waits, per step, for a column index and then for
+// the factor row it names, a dependent chain of global loads of which the
+// machine holds too few in flight (the gathers themselves mostly hit the L2).
+// The flat variant loads the item's row pointers, column indices and values
+// into registers at once (the item bounds are known), then walks the item's
+// nonzeros as one list, 16 gathers in flight per step, and writes out each row
+// as its end is passed.  Summation order within a row is the nonzero order,
+// as in the row-by-row kernel.
 #include <algorithm>
 #include <vector>
 
@@ -123,6 +133,98 @@ __global__ __launch_bounds__(256) void spmm_items(SpmmKArgs a) {
   }
 }
 
+constexpr int kMaxRowsPerItem = 256;
+constexpr int kFlatMaxNnz = 128;  // item nonzeros the flat kernel prefetches
+
+// Element k of a register array spread over the wave (element 64 m + l in lane
+// l of arr[m]); k is wave-uniform.
+template <int N, typename V>
+__device__ __forceinline__ V wave_elem(const V (&arr)[N], int k) {
+  V v = arr[0];
+#pragma unroll
+  for (int m = 1; m < N; m++)
+    if ((k >> 6) == m) v = arr[m];
+  return __builtin_bit_cast(V, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k & 63));
+}
+
+template <int VPL, typename TV, typename TX, bool VEC>
+__global__ __launch_bounds__(256) void spmm_flat(SpmmKArgs a) {
+  constexpr int UNR = VPL == 1 ? 16 : 8;
+  constexpr int MZ = kFlatMaxNnz / 64;
+  constexpr int MR = (kMaxRowsPerItem + 1 + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (it >= a.n_items) return;
+  const int K = a.K;
+  const TX* X = (const TX*)a.X;
+  const int4 item = a.items[it];
+  const int slot = a.slot[it];
+  const int r0 = item.x, nr = item.y - item.x;
+  const int j0 = item.z, nz = item.w - item.z;  // nz <= kFlatMaxNnz, nr <= kMaxRowsPerItem
+  int32_t pc[MZ], prp[MR];
+  float pv[MZ];
+#pragma unroll
+  for (int m = 0; m < MZ; m++) {
+    const int i = lane + 64 * m;
+    pc[m] = i < nz ? a.col[j0 + i] : 0;
+    pv[m] = i < nz ? ld_val<TV>(a.val, j0 + i) : 0.0f;
+  }
+#pragma unroll
+  for (int m = 0; m < MR; m++) {
+    const int i = lane + 64 * m;
+    prp[m] = i <= nr ? a.rowptr[r0 + i] : 0;
+  }
+  // end (item-local nonzero index) of local row r; a long row's segment ends at nz
+  auto row_end = [&](int r) {
+    const int e = wave_elem(prp, r + 1) - j0;
+    return e < nz ? e : nz;
+  };
+  floatx4 acc[VPL];
+#pragma unroll
+  for (int v = 0; v < VPL; v++) acc[v] = floatx4{0, 0, 0, 0};
+  int r = 0;
+  int rend = nr > 0 ? row_end(0) : nz;
+  auto flush = [&]() {
+    float* dst = slot >= 0 ? a.carry + (int64_t)slot * K : a.out + (int64_t)(r0 + r) * K;
+#pragma unroll
+    for (int v = 0; v < VPL; v++) {
+      const int cb = 4 * (lane + 64 * v);
+      if constexpr (VEC) {
+        if (cb < K) *(floatx4*)(dst + cb) = acc[v];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+          if (cb + e < K) dst[cb + e] = acc[v][e];
+      }
+      acc[v] = floatx4{0, 0, 0, 0};
+    }
+    r++;
+    rend = r < nr ? row_end(r) : nz;
+  };
+  for (int jb = 0; jb < nz; jb += UNR) {
+    floatx4 x[UNR][VPL];
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+      const int j = jb + u;
+      const int64_t col = j < nz ? wave_elem(pc, j) : 0;
+#pragma unroll
+      for (int v = 0; v < VPL; v++)
+        x[u][v] = j < nz ? ld_x4<TX, VEC>(X + col * K, 4 * (lane + 64 * v), K) : floatx4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+      const int j = jb + u;
+      if (j < nz) {
+        while (j >= rend && r < nr) flush();  // rows that end here, empty ones included
+        const float vv = wave_elem(pv, j);
+#pragma unroll
+        for (int v = 0; v < VPL; v++) acc[v] += vv * x[u][v];
+      }
+    }
+  }
+  while (r < nr) flush();
+}
+
 // One workgroup per long row: add its segments' partial rows.  Thread (v, sl)
 // sums columns 4v..4v+3 over segments sl, sl + S, ... (S slices, in order, four
 // loads in flight), then slice 0 adds the S slice sums in slice order: a fixed
@@ -187,9 +289,19 @@ hipError_t launch_t(const SpmmKArgs& a, bool vec, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int VPL, typename TV, typename TX>
+hipError_t launch_f(const SpmmKArgs& a, bool vec, hipStream_t s) {
+  const unsigned blocks = (unsigned)((a.n_items + 3) / 4);
+  if (blocks == 0) return hipSuccess;
+  if (vec) spmm_flat<VPL, TV, TX, true><<<blocks, 256, 0, s>>>(a);
+  else spmm_flat<VPL, TV, TX, false><<<blocks, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 template <typename TV, typename TX>
-hipError_t launch_k(const SpmmKArgs& a, bool vec, hipStream_t s) {
+hipError_t launch_k(const SpmmKArgs& a, bool vec, bool flat, hipStream_t s) {
   const int n4 = (a.K + 3) / 4;
+  if (flat && n4 > 32) return n4 <= 64 ? launch_f<1, TV, TX>(a, vec, s) : launch_f<2, TV, TX>(a, vec, s);
   if (n4 <= 1) return launch_t<1, 1, TV, TX>(a, vec, s);
   if (n4 <= 2) return launch_t<1, 2, TV, TX>(a, vec, s);
   if (n4 <= 4) return launch_t<1, 4, TV, TX>(a, vec, s);
@@ -199,8 +311,6 @@ hipError_t launch_k(const SpmmKArgs& a, bool vec, hipStream_t s) {
   if (n4 <= 64) return launch_t<1, 64, TV, TX>(a, vec, s);
   return launch_t<2, 64, TV, TX>(a, vec, s);  // K <= 512
 }
-
-constexpr int kMaxRowsPerItem = 256;
 
 }  // namespace
 
@@ -287,9 +397,11 @@ hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hip
   a.n_items = p.n_items;
   a.K = K;
   const size_t esz = t == Elem::F32 ? 4 : 2;
-  const bool vec = (K % 4 == 0) && (((uintptr_t)X) % (4 * esz) == 0);
-  hipError_t e = t == Elem::F32 ? launch_k<float, float>(a, vec, s)
-                                : launch_k<__bf16, __bf16>(a, vec, s);
+  const bool vec = (K % 4 == 0) && (((uintptr_t)X) % (4 * esz) == 0) &&
+                   ((uintptr_t)out % 16 == 0) && ((uintptr_t)p.carry % 16 == 0);
+  const bool flat = p.L <= kFlatMaxNnz;  // the flat kernel holds a whole item in registers
+  hipError_t e = t == Elem::F32 ? launch_k<float, float>(a, vec, flat, s)
+                                : launch_k<__bf16, __bf16>(a, vec, flat, s);
   if (e != hipSuccess) return e;
   if (p.n_fix > 0) {
     spmm_fixup<<<(unsigned)p.n_fix, kFixThreads, 0, s>>>(p.fix, p.n_fix, p.carry, out, K);

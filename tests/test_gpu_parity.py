@@ -131,11 +131,14 @@ def test_sparse_parity(cuda, K):
     plan.close()
 
 
-def test_sparse_products_with_empty_rows_and_columns(cuda):
+@pytest.mark.parametrize("K", [12, 150, 200, 300])
+def test_sparse_products_with_empty_rows_and_columns(cuda, K):
     """CSR with empty rows (terms never used) and empty columns (documents with
-    no terms) and one long row spanning many nnz chunks."""
+    no terms) and one long row spanning many nnz chunks.  K covers the narrow
+    (several nonzeros per wave step) and the wide (one nonzero per step,
+    prefetched item) product kernels, with and without 16-byte rows."""
     rng = np.random.default_rng(5)
-    V, D, K = 700, 500, 12
+    V, D = 700, 500
     dense = (rng.random((V, D)) < 0.02) * rng.random((V, D))
     dense[3, :] = rng.random(D) + 0.1  # one long row (crosses chunk boundaries)
     dense[::7, :] = 0.0          # empty rows
