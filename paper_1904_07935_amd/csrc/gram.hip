@@ -100,8 +100,7 @@ __global__ __launch_bounds__(kThreads) void gram_partial(const float* __restrict
     put(nxt);
     __syncthreads();
     if (s0 + kRS < r1) fetch(s0 + kRS, nxt);  // in flight during this stage's products
-#pragma unroll
-    for (int kk = 0; kk < kRS; kk += 2) {
+    auto ksteps = [&](int kk) {
       const float* row = stage + (kk + h) * P;
       float av[kMaxBlocksPerWave], bv[kMaxBlocksPerWave];
 #pragma unroll
@@ -112,6 +111,13 @@ __global__ __launch_bounds__(kThreads) void gram_partial(const float* __restrict
 #pragma unroll
       for (int k = 0; k < kMaxBlocksPerWave; k++)
         acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[k], bv[k], acc[k], 0, 0, 0);
+    };
+    if (s0 + kRS <= r1) {
+#pragma unroll
+      for (int kk = 0; kk < kRS; kk += 2) ksteps(kk);
+    } else {  // the chunk's ragged last stage: only its rows (the rest is zero)
+      const int nk = (int)(r1 - s0);
+      for (int kk = 0; kk < nk; kk += 2) ksteps(kk);
     }
   }
   // lane holds C block row 8 j + 4 h + i, column lane % 32, in acc[4 j + i]
