@@ -389,13 +389,36 @@ __global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
         float y[T];
 #pragma unroll
         for (int c = 0; c < T; c++) y[c] = part[lane * TP + c];
+        if (tw == T) {
+          // a full tile: no branch per step (a branch around a step makes the
+          // compiler copy all of y on both sides of it), and step t + 1's G row
+          // loaded during step t; the compiler barrier keeps later rows' loads
+          // from being hoisted further, which would exhaust the registers
+          float gr[T];
 #pragma unroll
-        for (int t = 0; t < T; t++) {
-          if (t < tw) {
+          for (int c = 1; c < T; c++) gr[c] = gt[c];
+#pragma unroll
+          for (int t = 0; t < T; t++) {
+            float gn[T];
+#pragma unroll
+            for (int c = t + 2; c < T; c++) gn[c] = gt[(t + 1) * TP + c];
+            asm volatile("" ::: "memory");
             const float x = fmaxf(eps, y[t]);
             y[t] = x;
 #pragma unroll
-            for (int c = t + 1; c < T; c++) y[c] -= x * gt[t * TP + c];
+            for (int c = t + 1; c < T; c++) y[c] -= x * gr[c];
+#pragma unroll
+            for (int c = t + 2; c < T; c++) gr[c] = gn[c];
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < T; t++) {
+            if (t < tw) {
+              const float x = fmaxf(eps, y[t]);
+              y[t] = x;
+#pragma unroll
+              for (int c = t + 1; c < T; c++) y[c] -= x * gt[t * TP + c];
+            }
           }
         }
 #pragma unroll
