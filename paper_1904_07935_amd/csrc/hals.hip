@@ -31,12 +31,13 @@
 // loop), so phase 2 is a chain of K chip-level reductions and their latency,
 // not arithmetic, bounds the kernel.  One launch of one 512-thread workgroup
 // per CU (all resident at once) splits the work by role:
-//   * column groups (few, about 2048 rows each) hold the tile's 32 columns of
-//     their rows in registers and run phase 2, exchanging one FP32 partial per
-//     column through tagged 64-bit slots.  They are the workgroups whose index
-//     is a multiple of 8 (then 8i+1, ...): the dispatcher places workgroup b on
-//     XCD b % 8, so up to 32 column groups share one XCD and its L2, where the
-//     exchange round trip is shortest.  Placement only affects speed.
+//   * column groups (as many as one XCD holds, at most 1792 rows each) hold
+//     the tile's 32 columns of their rows in registers and run phase 2,
+//     exchanging one FP32 partial per group and column through tagged 64-bit
+//     slots.  They are the workgroups whose index is a multiple of 8 (then
+//     8i+1, ...): the dispatcher places workgroup b on XCD b % 8, so up to 32
+//     column groups share one XCD and its L2, where the exchange round trip is
+//     shortest.  Placement only affects speed.
 //   * product groups (all others) compute the tile product of every row into
 //     a [rows, 32] hand-off buffer once the column groups have published the
 //     previous tile (the product reads those new columns).
@@ -79,39 +80,6 @@ __device__ __forceinline__ bool timed_out(const int32_t* status) {
   return (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 256) != 0;
 }
 
-// Fixed-order sum of the published partials of all groups (wave 0, all lanes),
-// groups <= 64 * MAXS.
-template <int MAXS>
-__device__ __forceinline__ float collect_sum(const unsigned long long* slots, int groups, int g,
-                                             unsigned tag, int par, int32_t* status) {
-  const int lane = threadIdx.x & 63;
-  const unsigned long long* base =
-      slots + (int64_t)(g % kSlotReplicas) * kSlotStride + (int64_t)par * groups;
-  unsigned long long v[MAXS];
-  int spins = 0;
-  bool done;
-  do {
-    done = true;
-#pragma unroll
-    for (int s = 0; s < MAXS; s++) {
-      const int i = lane + 64 * s;
-      if (i < groups) {
-        v[s] = __hip_atomic_load(base + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        done = done && ((unsigned)(v[s] >> 32) == tag);
-      }
-    }
-    // give up at once if any workgroup already timed out (bounded total wait)
-    if (!done && (++spins & 255) == 0 && timed_out(status)) break;
-  } while (!done && spins < kSpinLimit);
-  if (!done) atomicOr(status, 256);
-  float t = 0.0f;
-#pragma unroll
-  for (int s = 0; s < MAXS; s++)
-    if (lane + 64 * s < groups) t += __uint_as_float((unsigned)v[s]);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-  return t;
-}
 
 // Sum over all 64 lanes, the same in every lane, in a fixed order: DPP steps
 // within each row of 16 lanes (lane pairs, quads, halves), then the four row
@@ -457,8 +425,9 @@ constexpr int kWMaxRows = kWRowThreads * kWMaxRpt;  // rows per column group
 constexpr size_t kWSmemMin = 82 * 1024;             // > half the LDS: one group per CU
 constexpr int kWMaxColGroups = 64;
 
-// LDS (floats).  Column role: gt [T][TP] | wave slots [2][kWWaves] | total slots [2] |
-// protocol flag [2] (u64) | lane partials [2][kWWaves - 1][64].  Product role:
+// LDS (floats).  Column role: gt [T][TP] | wave sums [2][kWWaves] (in 2 kWWaves u64) |
+// column totals [2] (in 2 u64) | protocol flag [2] (u64) | lane partials
+// [2][kWWaves - 1][64].  Product role:
 // bp [kpad(K)][TP] | per-wave stash [kWWaves][jobs per wave][32][TP] (partial
 // products, then the transpose).
 constexpr size_t kLdsMax = 160 * 1024;
@@ -486,79 +455,75 @@ __device__ __forceinline__ int64_t quad_index(int64_t rows, int j, int v, int64_
   return ((int64_t)j * (T / 4) + v) * rows + r;
 }
 
-// Bounded wait of one wave for a tagged LDS slot; returns its value.
-__device__ __forceinline__ float lds_wait(unsigned long long* slot, unsigned tag, int32_t* status) {
-  unsigned long long v;
-  int spins = 0;
-  do {
-    v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-  } while ((unsigned)(v >> 32) != tag && ++spins < kSpinLimit);
-  if ((unsigned)(v >> 32) != tag && (threadIdx.x & 63) == 0) atomicOr(status, 256);
-  return __uint_as_float((unsigned)v);
-}
-
-__device__ __forceinline__ void lds_post(unsigned long long* slot, unsigned tag, float v) {
-  __hip_atomic_store(slot, pack_slot(tag, v), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
 
 // Column groups.  Waves 1..7 hold rows (RPT per thread) and run phase 2: per
 // column, each posts its partial sum of u_t^2, applies the previous column to
 // the rest of the tile while the exchange is in flight, and then needs the sum
-// of all partials.  Three exchange protocols, all summing in a fixed order (so
-// every wave of every group gets the bitwise-identical norm):
-//  * LOCAL (one column group): partials in tagged LDS slots, every row wave
-//    sums the seven of them.
-//  * XCD: all column groups run on one XCD (checked at kernel start): every
-//    row wave publishes its partial with a non-temporal store and sums all
-//    partials of all groups with non-temporal loads -- both served by that
-//    XCD's L2, which all its CUs share (about half the latency of device-scope
-//    accesses, which go past the L2; measured).
-//  * DEVICE (any placement): wave 0 sums the row waves' lane partials from LDS,
-//    exchanges one partial per group through device-scope slots and posts the
-//    total back in LDS.
-// No workgroup barrier separates two columns.  Tags and values share one 64-bit
-// word, so a slot is either this column's value or not yet ready.
+// of all partials.  Within the group, workgroup barriers order the steps (the
+// hardware barrier is cheaper than waves spinning on LDS flags).  Three
+// exchange protocols, all summing in a fixed order (so every wave of every
+// group gets the bitwise-identical norm):
+//  * LOCAL (one column group): each row wave writes its wave sum to LDS; after
+//    one barrier every row wave adds the seven in order.
+//  * XCD and DEVICE: the row waves write their lane partials to LDS; after a
+//    barrier wave 0 adds them (per lane in wave order, then across lanes),
+//    exchanges one partial per group with the other groups and writes the
+//    total to LDS, while the row waves apply the deferred update; a second
+//    barrier hands the total to the row waves.  XCD, when all column groups run
+//    on one XCD (checked at kernel start): non-temporal stores and loads,
+//    served by that XCD's L2, which all its CUs share (about half the latency
+//    of device-scope accesses, which go past the L2; measured), one partial per
+//    group in two replica slots.  DEVICE (any placement): device-scope atomics.
+// Slots hold tag and value in one 64-bit word, so a slot is either this
+// column's value or not yet ready.
 enum : int { kProtoLocal = 0, kProtoXcd = 1, kProtoDevice = 2 };
 constexpr int kSlotDev = 0;      // [2][n_col] group partials (device scope)
 constexpr int kSlotPlace = 256;  // [n_col] XCD of each column group (device scope)
-constexpr int kSlotXcd = 512;    // [2][7 n_col] row-wave partials (XCD-local)
-constexpr int kXcdMaxParts = 256;
-static_assert(kSlotXcd + 2 * kXcdMaxParts <= kSlotWords, "slot regions");
+constexpr int kSlotXcd = 512;    // [2 parities][2 replicas][64] group partials (XCD-local)
+static_assert(kSlotXcd + 2 * 128 <= kSlotWords, "slot regions");
+static_assert(kWMaxColGroups <= 64, "one slot per lane");
 static_assert(kWMaxColGroups <= 256 - kSlotDev / 2, "slot regions");
 
+
+// Sum of the n (<= 64) group partials of one column.  Each group publishes its
+// partial in two replica slots (base + rank, base + 64 + rank); the poller
+// keeps a non-temporal load of each replica in flight and checks them in turn,
+// reissuing each as soon as it has been checked, which finds a late partial
+// sooner than one load per L2 round trip (measured: W update 274 -> 246 us at
+// 26000 x 200).  Lanes >= n re-read slot n - 1.  Summed across lanes in a
+// fixed order.
 __device__ __forceinline__ float collect_xcd(const unsigned long long* base, int n, unsigned tag,
                                              int32_t* status) {
-  constexpr int MAXS = kXcdMaxParts / 64;
   const int lane = threadIdx.x & 63;
-  const int ns = (n + 63) / 64;  // uniform: slot rows in use
-  unsigned long long v[MAXS];
-#pragma unroll
-  for (int s = 0; s < MAXS; s++) v[s] = 0;  // tags are never 0 (epoch >= 1)
+  const int i = lane < n ? lane : n - 1;
+  const unsigned long long* pa = base + i;
+  const unsigned long long* pb = base + 64 + i;
+  unsigned long long va = __builtin_nontemporal_load(pa);
+  unsigned long long vb = __builtin_nontemporal_load(pb);
+  unsigned long long v = 0;
   int spins = 0;
-  bool done;
-  do {
-    asm volatile("" ::: "memory");  // reload every round
-    // every row's load in flight at once (lanes past n re-read slot n - 1),
-    // then one wait: a round costs one L2 round trip, not one per row
-#pragma unroll
-    for (int s = 0; s < MAXS; s++)
-      if (s < ns) {
-        const int i = lane + 64 * s;
-        v[s] = __builtin_nontemporal_load(base + (i < n ? i : n - 1));
-      }
-    bool mine = true;
-#pragma unroll
-    for (int s = 0; s < MAXS; s++)
-      if (s < ns) mine = mine && (lane + 64 * s >= n || (unsigned)(v[s] >> 32) == tag);
-    done = __all(mine);
-    if (!done && (++spins & 255) == 0 && timed_out(status)) break;
-  } while (!done && spins < kSpinLimit);
+  bool done = false;
+  while (true) {
+    // the register constraint orders each check after the reload issued before it
+    asm volatile("" : "+v"(va)::"memory");
+    if (__all(lane >= n || (unsigned)(va >> 32) == tag)) {
+      v = va;
+      done = true;
+      break;
+    }
+    va = __builtin_nontemporal_load(pa);
+    asm volatile("" : "+v"(vb)::"memory");
+    if (__all(lane >= n || (unsigned)(vb >> 32) == tag)) {
+      v = vb;
+      done = true;
+      break;
+    }
+    vb = __builtin_nontemporal_load(pb);
+    if ((++spins & 127) == 0 && timed_out(status)) break;
+    if (spins >= kSpinLimit) break;
+  }
   if (!done && lane == 0) atomicOr(status, 256);
-  float t = 0.0f;
-#pragma unroll
-  for (int s = 0; s < MAXS; s++)
-    if (lane + 64 * s < n) t += __uint_as_float((unsigned)v[s]);
-  return wave_sum(t);
+  return wave_sum(lane < n ? __uint_as_float((unsigned)v) : 0.0f);
 }
 
 template <int RPT, bool VEC, int PROTO>
@@ -567,11 +532,11 @@ __device__ __forceinline__ void column_tiles(const HalsWArgs& a, int rank, int n
   const bool xwave = w == 0;
   const int K = a.K;
   const int64_t rows = a.rows;
-  const int nparts = a.n_col * (kWWaves - 1);
   float* gt = lds;  // [T][TP] G of the tile
-  unsigned long long* lpart = (unsigned long long*)(lds + T * TP);  // [2][kWWaves]
-  unsigned long long* ltot = lpart + 2 * kWWaves;                   // [2]
-  float* lvals = (float*)(ltot + 4);                                // [2][kWWaves - 1][64]
+  unsigned long long* lpart = (unsigned long long*)(lds + T * TP);  // [2][kWWaves] slots
+  float* lsum = (float*)lpart;                                      // [2][kWWaves] (LOCAL)
+  float* ltot = (float*)(lpart + 2 * kWWaves);                      // [2] (two-level)
+  float* lvals = (float*)(lpart + 2 * kWWaves + 4);                 // [2][kWWaves - 1][64]
   const int64_t row0 = (int64_t)rank * a.rows_per_group;
   int64_t row1 = row0 + a.rows_per_group;
   if (row1 > rows) row1 = rows;
@@ -605,23 +570,7 @@ __device__ __forceinline__ void column_tiles(const HalsWArgs& a, int rank, int n
     // the product groups serving this column group: rank, rank + n_col, ...
     await_flags(a.flags + rank, (n_prod - rank + a.n_col - 1) / a.n_col, a.n_col,
                 tile_tag(a.epoch, j), a.status);
-    if (xwave) {
-      if constexpr (PROTO == kProtoDevice) {
-        for (int t = 0; t < tw; t++) {
-          const unsigned ctag = (a.epoch << 10) | (unsigned)(a0 + t);
-          const int par = (a0 + t) & 1;
-          if (lane >= 1 && lane < kWWaves) lds_wait(lpart + par * kWWaves + lane, ctag, a.status);
-          // the group's partial: per lane over the row waves in order, then across lanes
-          float g = 0.0f;
-#pragma unroll
-          for (int i = 0; i < kWWaves - 1; i++) g += lvals[(par * (kWWaves - 1) + i) * 64 + lane];
-          g = wave_sum(g);
-          if (lane < kSlotReplicas) publish(a.slots + kSlotDev, a.n_col, rank, ctag, par, g, lane);
-          const float tot = collect_sum64(a.slots + kSlotDev, a.n_col, rank, ctag, par, a.status);
-          if (lane == 0) lds_post(ltot + par, ctag, tot);
-        }
-      }
-    } else {
+    if (!xwave) {
       // this group's rows of the tile's product (one contiguous run of rows per wave)
 #pragma unroll
       for (int q = 0; q < RPT; q++) {
@@ -632,37 +581,27 @@ __device__ __forceinline__ void column_tiles(const HalsWArgs& a, int rank, int n
           for (int e = 0; e < 4; e++) y[q][4 * v + e] = f[e];
         }
       }
-      // invariant at step t: y[q][t] = u_t (clipped, not normalised) and ss = this
-      // thread's part of sum u_t^2; columns > t lack only the pending x_{t-1} term
-      float ss = 0.0f;
+    }
+    // invariant at step t: y[q][t] = u_t (clipped, not normalised) and ss = this
+    // thread's part of sum u_t^2; columns > t lack only the pending x_{t-1} term
+    float ss = 0.0f;
 #pragma unroll
-      for (int q = 0; q < RPT; q++) {
-        const float u = fmaxf(eps, y[q][0]);
-        y[q][0] = u;
-        ss += valid[q] ? u * u : 0.0f;
-      }
-      float xprev[RPT];
+    for (int q = 0; q < RPT; q++) {
+      const float u = fmaxf(eps, y[q][0]);
+      y[q][0] = u;
+      ss += valid[q] ? u * u : 0.0f;
+    }
+    float xprev[RPT];
 #pragma unroll
-      for (int q = 0; q < RPT; q++) xprev[q] = 0.0f;
+    for (int q = 0; q < RPT; q++) xprev[q] = 0.0f;
 #pragma unroll
-      for (int t = 0; t < T; t++) {
-        if (t < tw) {
-          const unsigned ctag = (a.epoch << 10) | (unsigned)(a0 + t);
-          const int par = (a0 + t) & 1;
-          if constexpr (PROTO == kProtoDevice) {
-            lvals[(par * (kWWaves - 1) + (w - 1)) * 64 + lane] = ss;
-            if (lane == 0) lds_post(lpart + par * kWWaves + w, ctag, 0.0f);
-          } else if constexpr (PROTO == kProtoXcd) {
-            const float mine = wave_sum(ss);
-            if (lane == 0)
-              __builtin_nontemporal_store(
-                  pack_slot(ctag, mine),
-                  a.slots + kSlotXcd + par * nparts + rank * (kWWaves - 1) + (w - 1));
-          } else {
-            const float mine = wave_sum(ss);
-            if (lane == 0) lds_post(lpart + par * kWWaves + w, ctag, mine);
-          }
-          // off the critical path: the previous column's contribution to columns > t
+    for (int t = 0; t < T; t++) {
+      if (t < tw) {
+        const unsigned ctag = (a.epoch << 10) | (unsigned)(a0 + t);
+        const int par = (a0 + t) & 1;
+        // off the critical path, while the exchange is in flight: the previous
+        // column's contribution to columns > t
+        auto deferred = [&]() {
           if (t > 0) {
 #pragma unroll
             for (int c = t + 1; c < T; c++) {
@@ -671,26 +610,56 @@ __device__ __forceinline__ void column_tiles(const HalsWArgs& a, int rank, int n
               for (int q = 0; q < RPT; q++) y[q][c] -= xprev[q] * gv;
             }
             // finished here, before the wait: left to itself the compiler sinks
-            // these products below the polling loop, onto the critical path
+            // these products below the wait, onto the critical path
 #pragma unroll
             for (int c = t + 1; c < T; c++)
 #pragma unroll
               for (int q = 0; q < RPT; q++) asm volatile("" : "+v"(y[q][c]));
           }
-          const float gnext = t + 1 < T ? gt[t * TP + t + 1] : 0.0f;
-          float tot;
-          if constexpr (PROTO == kProtoDevice) {
-            tot = lds_wait(ltot + par, ctag, a.status);
-          } else if constexpr (PROTO == kProtoXcd) {
-            tot = collect_xcd(a.slots + kSlotXcd + par * nparts, nparts, ctag, a.status);
-          } else {
-            float part = 0.0f;
-            if (lane >= 1 && lane < kWWaves) part = lds_wait(lpart + par * kWWaves + lane, ctag, a.status);
-            tot = 0.0f;
-#pragma unroll
-            for (int i = 1; i < kWWaves; i++)
-              tot += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, part), i));
+        };
+        float tot = 0.0f;
+        {
+          if (!xwave) {
+            if constexpr (PROTO == kProtoLocal) {
+              const float mine = wave_sum(ss);
+              if (lane == 0) lsum[par * kWWaves + w] = mine;
+            } else {
+              lvals[(par * (kWWaves - 1) + (w - 1)) * 64 + lane] = ss;
+            }
           }
+          __syncthreads();
+          if (xwave) {
+            if constexpr (PROTO != kProtoLocal) {
+              // the group's partial: per lane over the row waves in order, then across lanes
+              float g = 0.0f;
+#pragma unroll
+              for (int i = 0; i < kWWaves - 1; i++) g += lvals[(par * (kWWaves - 1) + i) * 64 + lane];
+              g = wave_sum(g);
+              float tg;
+              if constexpr (PROTO == kProtoXcd) {
+                unsigned long long* sb = a.slots + kSlotXcd + par * 128;
+                if (lane < 2) __builtin_nontemporal_store(pack_slot(ctag, g), sb + 64 * lane + rank);
+                tg = collect_xcd(sb, a.n_col, ctag, a.status);
+              } else {
+                if (lane < kSlotReplicas) publish(a.slots + kSlotDev, a.n_col, rank, ctag, par, g, lane);
+                tg = collect_sum64(a.slots + kSlotDev, a.n_col, rank, ctag, par, a.status);
+              }
+              if (lane == 0) ltot[par] = tg;
+            }
+          } else {
+            deferred();
+          }
+          if constexpr (PROTO == kProtoLocal) {
+            if (!xwave)
+#pragma unroll
+              for (int i = 1; i < kWWaves; i++) tot += lsum[par * kWWaves + i];
+          } else {
+            __syncthreads();
+            if (!xwave) tot = ltot[par];
+          }
+        }
+        if (!xwave) {
+          const float gnext = t + 1 < T ? gt[t * TP + t + 1] : 0.0f;
           const float rn = 1.0f / sqrtf(tot);
           ss = 0.0f;
 #pragma unroll
@@ -706,6 +675,8 @@ __device__ __forceinline__ void column_tiles(const HalsWArgs& a, int rank, int n
           }
         }
       }
+    }
+    if (!xwave) {
       // the finished tile to its hand-off region; product groups copy it into X
 #pragma unroll
       for (int q = 0; q < RPT; q++) {
@@ -726,7 +697,7 @@ __device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n
   const int tid = threadIdx.x, lane = tid & 63;
   unsigned long long* lpart = (unsigned long long*)(lds + T * TP);
   int* lflag = (int*)(lpart + 2 * kWWaves + 2);
-  if (tid < 2 * kWWaves + 2) lpart[tid] = 0;  // no stale tags (the barrier below orders it)
+  if (tid < 2 * kWWaves + 2) lpart[tid] = 0;  // exchange words and the protocol flag
   if constexpr (LOCAL) {
     __syncthreads();
     column_tiles<RPT, VEC, kProtoLocal>(a, rank, n_prod, lds);
@@ -751,7 +722,7 @@ __device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n
       if (!done && lane == 0) atomicOr(a.status, 256);
       const unsigned first = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 0);
       const bool same = __all(lane >= a.n_col || (unsigned)v == first);
-      if (lane == 0) *lflag = same && a.n_col * (kWWaves - 1) <= kXcdMaxParts;
+      if (lane == 0) *lflag = same;
     }
     __syncthreads();
     if (*lflag) column_tiles<RPT, VEC, kProtoXcd>(a, rank, n_prod, lds);
