@@ -515,11 +515,13 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
   } while (0)
 
   // W kernel: one group per CU; column groups of at most
-  // hals_w_max_rows_per_group() rows each (more, smaller ones on request)
+  // hals_w_max_rows_per_group() rows each (a count set on request, at least
+  // what the rows need)
   int ncol = hals_w_column_groups(s.V, cus);
   if (const char* env = getenv("NMF_W_COLUMN_GROUPS")) {
+    const int need = (int)((s.V + hals_w_max_rows_per_group() - 1) / hals_w_max_rows_per_group());
     const int v = atoi(env);
-    if (v > ncol) ncol = (int)std::min<int64_t>(std::min(v, hals_w_max_column_groups()), s.V);
+    if (v > 0) ncol = (int)std::min<int64_t>(std::min(std::max(v, need), hals_w_max_column_groups()), s.V);
   }
   const int64_t rpg = hals_w_rows_per_group(s.V, ncol);
   ncol = (int)((s.V + rpg - 1) / rpg);
