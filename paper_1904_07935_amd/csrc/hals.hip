@@ -309,20 +309,26 @@ __global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
 
   const int chunk = ((kp + 3) / 4 + 7) / 8 * 8;  // contraction per wave, a multiple of 8
   const int lb = w * chunk, le = lb + chunk < kp ? lb + chunk : kp;
+  // wave 0: a tile's Bterm in the product's lane layout, loaded one tile ahead
+  auto load_bt = [&](int jt, float (&b)[16]) {
+    const int at = jt * T, twt = at + T < K ? T : K - at;
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int rl = 8 * jj + 4 * h + i;
+        b[4 * jj + i] = (rl < nr && m < twt) ? a.Bterm[(row0 + rl) * K + at + m] : 0.0f;
+      }
+  };
+  float btn[16];
+  if (w == 0) load_bt(0, btn);
   for (int j = 0; j < ntiles; j++) {
     const int a0 = j * T, tw = a0 + T < K ? T : K - a0;
     const float* gt = gtb + (j & 1) * T * TP;
-    // wave 0: this tile's Bterm in the product's lane layout
     float bt[16];
-    if (w == 0) {
 #pragma unroll
-      for (int jj = 0; jj < 4; jj++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const int rl = 8 * jj + 4 * h + i;
-          bt[4 * jj + i] = (rl < nr && m < tw) ? a.Bterm[(row0 + rl) * K + a0 + m] : 0.0f;
-        }
-    }
+    for (int e = 0; e < 16; e++) bt[e] = btn[e];
+    if (w == 0 && j + 1 < ntiles) load_bt(j + 1, btn);
     // the tile product, contraction [lb, le) of this wave
     floatx16 acc;
 #pragma unroll
