@@ -240,11 +240,14 @@ __device__ __forceinline__ floatx16 block_product(const float* __restrict__ xr, 
 // product on the matrix cores with the contraction split over the four waves,
 // Bterm added, then phase 2 by wave 0 (one lane per row, the tile's columns in
 // registers) while waves 1..3 stage the next tile's panel.
-// LDS (floats): xs [32][XP] | bp [kpad(K)][TP] | gt [2][T][TP] | part [3][32][TP],
-// XP = 32 * ntiles + 1 (odd: conflict-free row and column access).
+// LDS (floats): xs [32][XP] | bp [kpad(K)][TP] | gt [2][T][GP] | part [3][32][TP],
+// XP = 32 * ntiles + 1 (odd: conflict-free row and column access); GP = T + 4
+// keeps every G row 16-byte aligned (phase 2 reads G rows, the same address in
+// every lane, as 16-byte vectors).
 __host__ __device__ inline int h_xp(int K) { return 32 * ((K + T - 1) / T) + 1; }
+constexpr int GP = T + 4;
 __host__ __device__ inline size_t h_smem_floats(int K) {
-  return (size_t)kRowsH * h_xp(K) + (size_t)kpad(K) * TP + 2 * T * TP + 3 * 32 * TP;
+  return (size_t)kRowsH * h_xp(K) + (size_t)kpad(K) * TP + 2 * T * GP + 3 * 32 * TP;
 }
 
 __device__ __forceinline__ void copy_panel(const float* __restrict__ panel, const float* __restrict__ gblk,
@@ -260,14 +263,7 @@ __device__ __forceinline__ void copy_panel(const float* __restrict__ panel, cons
     d[3] = v[3];
   }
   const floatx4* gs = (const floatx4*)(gblk + (int64_t)j * T * T);
-  for (int i = t0; i < T * T / 4; i += nt) {
-    const floatx4 v = gs[i];
-    float* d = gt + (4 * i / T) * TP + (4 * i) % T;
-    d[0] = v[0];
-    d[1] = v[1];
-    d[2] = v[2];
-    d[3] = v[3];
-  }
+  for (int i = t0; i < T * T / 4; i += nt) *(floatx4*)(gt + (4 * i / T) * GP + (4 * i) % T) = gs[i];
 }
 
 template <bool VEC>
@@ -280,7 +276,7 @@ __global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
   float* xs = smem_raw;
   float* bp = xs + kRowsH * XP;
   float* gtb = bp + kp * TP;
-  float* part = gtb + 2 * T * TP;
+  float* part = gtb + 2 * T * GP;
   const float eps = a.eps;
 
   // the group's rows, zero-padded to 32 * ntiles columns
@@ -324,7 +320,7 @@ __global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
   if (w == 0) load_bt(0, btn);
   for (int j = 0; j < ntiles; j++) {
     const int a0 = j * T, tw = a0 + T < K ? T : K - a0;
-    const float* gt = gtb + (j & 1) * T * TP;
+    const float* gt = gtb + (j & 1) * T * GP;
     float bt[16];
 #pragma unroll
     for (int e = 0; e < 16; e++) bt[e] = btn[e];
@@ -370,12 +366,20 @@ __global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
           // from being hoisted further, which would exhaust the registers
           float gr[T];
 #pragma unroll
-          for (int c = 1; c < T; c++) gr[c] = gt[c];
+          for (int q = 0; q < T / 4; q++) {
+            const floatx4 v = *(const floatx4*)(gt + 4 * q);
+#pragma unroll
+            for (int e = 0; e < 4; e++) gr[4 * q + e] = v[e];
+          }
 #pragma unroll
           for (int t = 0; t < T; t++) {
             float gn[T];
 #pragma unroll
-            for (int c = t + 2; c < T; c++) gn[c] = gt[(t + 1) * TP + c];
+            for (int q = (t + 2) / 4; q < T / 4; q++) {
+              const floatx4 v = *(const floatx4*)(gt + (t + 1) * GP + 4 * q);
+#pragma unroll
+              for (int e = 0; e < 4; e++) gn[4 * q + e] = v[e];
+            }
             asm volatile("" ::: "memory");
             const float x = fmaxf(eps, y[t]);
             y[t] = x;
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
               const float x = fmaxf(eps, y[t]);
               y[t] = x;
 #pragma unroll
-              for (int c = t + 1; c < T; c++) y[c] -= x * gt[t * TP + c];
+              for (int c = t + 1; c < T; c++) y[c] -= x * gt[t * GP + c];
             }
           }
         }
@@ -401,7 +405,7 @@ __global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
       }
     } else if (j + 1 < ntiles) {
       // waves 1..3: the next tile's panel (bp is free once every wave has its product)
-      copy_panel(a.panel, a.gblk, K, j + 1, bp, gtb + ((j + 1) & 1) * T * TP, tid - 64, 192);
+      copy_panel(a.panel, a.gblk, K, j + 1, bp, gtb + ((j + 1) & 1) * T * GP, tid - 64, 192);
     }
     __syncthreads();
   }

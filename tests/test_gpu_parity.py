@@ -243,3 +243,22 @@ def test_input_validation_on_device(cuda):
         Plan(Matrix(2, 5, rowptr=rp, col=cl, val=vl), torch.rand(2, 1, device=cuda),
              torch.rand(5, 1, device=cuda))
     assert e.value.status == -2
+    # a duplicate column in a row longer than one wave step, a column out of
+    # range, a negative value, and end pointers that disagree with nnz
+    n = 150
+    cols = list(range(n))
+    cols[100] = cols[99]
+    cases = [  # (row pointers, columns, values, D, expected status)
+        ([0, n, n], cols, [1.0] * n, n + 1, -2),
+        ([0, 2, 3], [0, 5, 1], [1.0] * 3, 5, -2),
+        ([0, 2, 3], [0, 1, 2], [1.0, -1.0, 1.0], 4, -5),
+        ([0, 2, 2], [0, 1, 2], [1.0] * 3, 4, -2),
+    ]
+    for rows_ptr, cols_, vals, Dm, code in cases:
+        rp = torch.tensor(rows_ptr, dtype=torch.int32, device=cuda)
+        cl = torch.tensor(cols_, dtype=torch.int32, device=cuda)
+        vl = torch.tensor(vals, dtype=torch.float32, device=cuda)
+        with pytest.raises(NmfError) as e:
+            Plan(Matrix(2, Dm, rowptr=rp, col=cl, val=vl), torch.rand(2, 1, device=cuda),
+                 torch.rand(Dm, 1, device=cuda))
+        assert e.value.status == code, (rows_ptr, code, e.value.status)
