@@ -670,7 +670,9 @@ __device__ __forceinline__ void column_tiles(const HalsWArgs& a, int rank, int n
         }
         if (!xwave) {
           const float gnext = t + 1 < T ? gt[t * TP + t + 1] : 0.0f;
-          const float rn = 1.0f / sqrtf(tot);
+          // hardware reciprocal square root (within about 1 ulp; every wave of
+          // every group computes it from the identical total)
+          const float rn = __builtin_amdgcn_rsqf(tot);
           ss = 0.0f;
 #pragma unroll
           for (int q = 0; q < RPT; q++) {
