@@ -117,6 +117,25 @@ def test_w_column_groups_across_xcds_match_oracle(cuda, monkeypatch):
     plan.close()
 
 
+@pytest.mark.parametrize("V, groups", [(40000, 32), (60000, 34)])
+def test_w_half_four_rows_per_thread_matches_oracle(cuda, V, groups):
+    """Corpora large enough that a column group holds more than two rows per
+    thread (the four-row variant of the W kernel): 32 column groups on one XCD
+    (the XCD-local exchange), and 34 groups, more than one XCD holds (the
+    device-scope exchange).  One W half against the oracle's."""
+    c = datagen.bag_of_words(V, 6000, 1.1, 77.0, 7)
+    K = 48
+    W0, H0 = sparse_init(c, K)
+    plan = gpu_plan(c.A, W0, H0, cuda)
+    assert plan.info()["w_groups"] == groups
+    plan.half("W")
+    Wo, _, _ = hals.w_half(oracle_A(c.A), hals.normalize_columns(W0), np.asarray(H0, np.float64), EPS)
+    got = _np(plan.W)
+    assert rel_fro(got, Wo) <= 5e-4
+    np.testing.assert_allclose(np.linalg.norm(got, axis=0), 1.0, rtol=1e-5)
+    plan.close()
+
+
 @pytest.mark.parametrize("K", [5, 24, 64])
 def test_sparse_parity(cuda, K):
     c = small_bow()
