@@ -14,6 +14,7 @@ Prints one JSON line:
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -60,10 +61,15 @@ def step_work(step, V, D, K, nnz):
 
 
 def source_digest():
+    """Digest of the kernel sources' code (comments and blank lines left out),
+    which the stored HBM counters must match to be reported."""
     h = hashlib.sha256()
     for f in ("hals.hip", "spmm.hip", "gemm.hip"):
-        with open(os.path.join(ROOT, "paper_1904_07935_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1904_07935_amd", "csrc", f)) as fh:
+            txt = fh.read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", "", txt)
+        h.update("\n".join(l.rstrip() for l in txt.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
 
 

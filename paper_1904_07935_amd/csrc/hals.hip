@@ -66,10 +66,10 @@ __device__ __forceinline__ unsigned long long pack_slot(unsigned tag, float v) {
   return ((unsigned long long)tag << 32) | (unsigned long long)__float_as_uint(v);
 }
 
-// The slot array is replicated kSlotReplicas times (kSlotStride apart): every
-// group writes its partial into all replicas and polls only replica g %
-// kSlotReplicas, so the polling traffic of all groups does not converge on the
-// same few cache lines.  Called by lanes 0..kSlotReplicas-1 of one wave.
+// Device-scope exchange (column groups on several XCDs).  The slot array can
+// be replicated kSlotReplicas times (kSlotStride apart; one copy at present):
+// every group writes its partial into all replicas and polls only replica
+// g % kSlotReplicas.  Called by lanes 0..kSlotReplicas-1 of one wave.
 __device__ __forceinline__ void publish(unsigned long long* slots, int groups, int g, unsigned tag,
                                         int par, float mine, int replica) {
   __hip_atomic_store(slots + (int64_t)replica * kSlotStride + (int64_t)par * groups + g,
@@ -543,7 +543,7 @@ __device__ __forceinline__ void column_tiles(const HalsWArgs& a, int rank, int n
   const int K = a.K;
   const int64_t rows = a.rows;
   float* gt = lds;  // [T][TP] G of the tile
-  unsigned long long* lpart = (unsigned long long*)(lds + T * TP);  // [2][kWWaves] slots
+  unsigned long long* lpart = (unsigned long long*)(lds + T * TP);  // exchange words
   float* lsum = (float*)lpart;                                      // [2][kWWaves] (LOCAL)
   float* ltot = (float*)(lpart + 2 * kWWaves);                      // [2] (two-level)
   float* lvals = (float*)(lpart + 2 * kWWaves + 4);                 // [2][kWWaves - 1][64]
