@@ -47,9 +47,11 @@ def test_bf16_products_dense_error_stated(cuda):
     p16.close()
 
 
-def test_bf16_products_sparse_error_stated(cuda):
+@pytest.mark.parametrize("K", [24, 160])
+def test_bf16_products_sparse_error_stated(cuda, K):
+    """K = 24: several nonzeros per wave step; K = 160: the one-nonzero-per-step
+    kernel with its prefetched item, gathering BF16 rows."""
     c = small_bow()
-    K = 24
     W0, H0 = sparse_init(c, K)
     rel_or, _ = oracle_run(c.A, W0, H0, 8)
     p16 = gpu_plan(c.A, W0, H0, cuda, precision="bf16")
