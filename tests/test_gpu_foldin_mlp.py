@@ -35,11 +35,13 @@ def _fold_setup(cuda, K=16, sweeps=5, Dn=400, seed=7):
     return c, W, new, plan
 
 
-def test_foldin_given_init_matches_oracle(cuda):
+@pytest.mark.parametrize("K", [16, 200])
+def test_foldin_given_init_matches_oracle(cuda, K):
+    """K = 200 is the fold-in workload's rank (the wide sparse-product kernel)."""
     import torch
 
     from paper_1904_07935_amd.api import Matrix
-    c, W, new, plan = _fold_setup(cuda)
+    c, W, new, plan = _fold_setup(cuda, K=K)
     K, Dn = W.shape[1], new.rows
     Anew = rows_csr_to_oracle(new)
     _, H0 = datagen.uniform_init_matched(c.A.rows, Dn, K, datagen.mean_value(new), seed=4)
