@@ -15,7 +15,8 @@
  *   Ht [D, K] (row d holds document d's K weights), so that every row of both
  *   factors is K-contiguous.
  * - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work is
- *   enqueued on it; only calls that return host values synchronise it.
+ *   enqueued on it; only calls that return host values, and nmf_sweep (which
+ *   reads the device status word once per call), synchronise it.
  * - Every call returns an int status (nmf_status).  No exception crosses the
  *   ABI.  On error, nmf_last_error() returns a thread-local message.  After a
  *   HIP runtime error or a device-side timeout a plan is poisoned and every
@@ -99,19 +100,26 @@ int nmf_workspace_bytes(const nmf_matrix* A, int K, int precision, size_t* bytes
  *              transposed CSR, BF16 copies and reduction scratch; owned by the
  *              caller and bound to the plan until nmf_destroy.
  * Validates shapes, alignment and (for CSR) the index structure on the device,
- * builds the CSR of A^T, computes ||A||_F^2.  Synchronises `stream`.           */
+ * builds the CSR of A^T, computes ||A||_F^2.  Synchronises `stream`.
+ * Errors: NMF_E_NUMERIC for a negative/NaN/Inf entry of A, W or Ht, for an
+ * all-zero A, or for a column of W with zero norm (it cannot be normalised).  */
 int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision,
              float* W, float* Ht, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Run n_sweeps outer iterations of Alg. 1 (H half, then W half) in place on the
  * plan's W and Ht.  If rel_obj is non-NULL it receives, per sweep, the relative
- * objective sqrt(sum (A-WH)^2 / sum A^2) of Sec. 6.2 after that sweep, and the
- * call synchronises the stream; with NULL nothing is synchronised.            */
+ * objective sqrt(sum (A-WH)^2 / sum A^2) of Sec. 6.2 after that sweep.  Every
+ * call ends by reading the device status word (one 4-byte copy, one stream
+ * synchronisation): a W update whose device-side wait timed out -- in this
+ * call or in an earlier nmf_half -- returns NMF_E_TIMEOUT and poisons the
+ * plan.  A non-finite objective returns NMF_E_NUMERIC.                       */
 int nmf_sweep(nmf_plan plan, int n_sweeps, double* rel_obj);
 
 /* Run one half of a sweep: NMF_HALF_H forms R = A^T W and S = W^T W and updates
  * every row of H (Alg. 1, H loop); NMF_HALF_W forms P = A H^T and Q = H H^T and
- * updates every column of W with normalisation (Alg. 1, W loop).  Enqueue only. */
+ * updates every column of W with normalisation (Alg. 1, W loop).  Enqueue only:
+ * a device-side timeout of its W update is reported by the next nmf_sweep or
+ * nmf_objective on the plan.                                                  */
 int nmf_half(nmf_plan plan, int which);
 
 /* Objective of Eq. 2, 0.5 ||A - W H||_F^2, and the relative objective of
@@ -145,6 +153,14 @@ int nmf_profile(nmf_plan plan, int enable);
  * stream and resets the record.                                              */
 int nmf_profile_read(nmf_plan plan, double* ms_total, int64_t* launches);
 int nmf_set_stream(nmf_plan plan, void* stream);
+/* Fault injection for tests of the error paths: ORs `bits` into the plan's
+ * device status word, in stream order.  The only accepted value is
+ * NMF_STATUS_TIMEOUT, the bit a timed-out device-side wait sets: the next W
+ * update's bounded waits then give up at once (every kernel still runs to its
+ * end; the factors are left unspecified) and the next nmf_sweep or
+ * nmf_objective returns NMF_E_TIMEOUT and poisons the plan.                  */
+#define NMF_STATUS_TIMEOUT 256
+int nmf_inject_status(nmf_plan plan, int32_t bits);
 int nmf_destroy(nmf_plan plan);
 const char* nmf_last_error(void);
 
@@ -158,19 +174,29 @@ const char* nmf_last_error(void);
  *               NMF_FOLDIN_WTA    max(eps, A_new^T W)   (non-learned warm start)
  *               NMF_FOLDIN_MLP    ||r|| * mlp(r / ||r||), r = row of A_new^T W,
  *                                 with the network in `mlp_params`
- *   n_sweeps  H-only sweeps to run after the initialisation.
- *   rel_trace host [n_sweeps+1] or NULL: relative objective of the fold-in
- *             problem after initialisation (index 0) and after each sweep;
- *             computed on the device, copied once at the end (synchronises).
- *   workspace >= nmf_foldin_workspace_bytes().                               */
+ *   max_sweeps  H-only sweeps to run at most after the initialisation.
+ *   tol       0: run exactly max_sweeps sweeps (no per-sweep synchronisation).
+ *             > 0: stop after the first sweep that lowers the relative
+ *             objective of the fold-in problem by less than tol (absolute, in
+ *             relative-objective units); the objective is then computed and
+ *             read back after every sweep (one synchronisation per sweep).
+ *   sweeps_done  host int or NULL: the number of sweeps run.
+ *   rel_trace host [max_sweeps+1] or NULL: relative objective of the fold-in
+ *             problem after initialisation (index 0) and after each sweep run
+ *             (entries past *sweeps_done are left untouched); computed on the
+ *             device (synchronises).
+ *   workspace >= nmf_foldin_workspace_bytes().
+ * Errors: NMF_E_ARG (tol < 0 or not finite, bad mode), NMF_E_SHAPE (the new
+ * documents' CSR structure or V), NMF_E_NUMERIC (negative/NaN entries, or a
+ * non-finite objective when tol > 0).                                        */
 #define NMF_FOLDIN_GIVEN 0
 #define NMF_FOLDIN_WTA 1
 #define NMF_FOLDIN_MLP 2
 int nmf_foldin_workspace_bytes(nmf_plan plan, const nmf_matrix* AnewT, int mlp_hidden,
                                size_t* bytes);
 int nmf_foldin(nmf_plan plan, const nmf_matrix* AnewT, float* Ht_new, int init_mode,
-               const void* mlp_params, int mlp_hidden, int n_sweeps, double* rel_trace,
-               void* workspace, size_t workspace_bytes);
+               const void* mlp_params, int mlp_hidden, int max_sweeps, double tol,
+               int* sweeps_done, double* rel_trace, void* workspace, size_t workspace_bytes);
 
 /* ------------------------------------------------- warm-start network ----
  * y = softplus(W2 GELU(W1 x + b1) + b2), x in R^K, hidden units `hidden`
@@ -198,7 +224,7 @@ int nmf_mlp_init(void* params, int K, int hidden, uint64_t seed, void* stream);
 int nmf_mlp_refresh(void* params, int K, int hidden, void* stream);
 int nmf_mlp_workspace_bytes(int K, int hidden, int64_t batch, size_t* bytes);
 /* Yhat [N,K] = network(X [N,K]); FP32 in/out, batched internally.            */
-int nmf_mlp_forward(const void* params, int K, int hidden, const float* X, float* Yhat,
+int nmf_mlp_predict(const void* params, int K, int hidden, const float* X, float* Yhat,
                     int64_t N, void* workspace, size_t workspace_bytes, void* stream);
 /* Loss and gradients of one batch (N <= the batch the workspace was sized for):
  * grads has the layout of the FP32 masters.  *loss (host) synchronises.      */

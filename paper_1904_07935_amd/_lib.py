@@ -61,17 +61,18 @@ SIGNATURES = {
     "nmf_intermediates": [_P, POINTER(_P), POINTER(_P), POINTER(_P), POINTER(_P)],
     "nmf_plan_info": [_P, POINTER(nmf_info)],
     "nmf_set_stream": [_P, _P],
+    "nmf_inject_status": [_P, c_int32],
     "nmf_destroy": [_P],
     "nmf_profile": [_P, c_int],
     "nmf_profile_read": [_P, POINTER(c_double), POINTER(c_int64)],
     "nmf_foldin_workspace_bytes": [_P, POINTER(nmf_matrix), c_int, POINTER(c_size_t)],
-    "nmf_foldin": [_P, POINTER(nmf_matrix), _P, c_int, _P, c_int, c_int, POINTER(c_double), _P,
-                   c_size_t],
+    "nmf_foldin": [_P, POINTER(nmf_matrix), _P, c_int, _P, c_int, c_int, c_double, POINTER(c_int),
+                   POINTER(c_double), _P, c_size_t],
     "nmf_mlp_param_bytes": [c_int, c_int, POINTER(nmf_mlp_layout)],
     "nmf_mlp_init": [_P, c_int, c_int, c_uint64, _P],
     "nmf_mlp_refresh": [_P, c_int, c_int, _P],
     "nmf_mlp_workspace_bytes": [c_int, c_int, c_int64, POINTER(c_size_t)],
-    "nmf_mlp_forward": [_P, c_int, c_int, _P, _P, c_int64, _P, c_size_t, _P],
+    "nmf_mlp_predict": [_P, c_int, c_int, _P, _P, c_int64, _P, c_size_t, _P],
     "nmf_mlp_loss_grad": [_P, c_int, c_int, _P, _P, c_int64, _P, POINTER(c_double), _P, c_size_t,
                           _P],
     "nmf_mlp_adam_step": [_P, c_int, c_int, _P, c_float, _P],

@@ -142,14 +142,24 @@ class Plan:
         L.call("nmf_profile_read", self.h, ms, cnt)
         return {name: (ms[i], cnt[i]) for i, name in enumerate(L.STEP_NAMES)}
 
+    def inject_status(self, bits=256):
+        """Fault injection for error-path tests (NMF_STATUS_TIMEOUT)."""
+        self._sync_stream()
+        L.call("nmf_inject_status", self.h, int(bits))
+
     def info(self):
         i = L.nmf_info()
         L.call("nmf_plan_info", self.h, byref(i))
         return {f: getattr(i, f) for f, _ in L.nmf_info._fields_}
 
     def foldin(self, AnewT: Matrix, Ht_new: torch.Tensor, init="given", mlp=None, n_sweeps=10,
-               trace=True):
-        """H-only sweeps for new documents (rows of AnewT) with this plan's W fixed."""
+               trace=True, tol=0.0):
+        """H-only sweeps for new documents (rows of AnewT) with this plan's W fixed.
+
+        ``n_sweeps`` is the most sweeps run; with ``tol > 0`` the call stops
+        after the first sweep lowering the relative objective by less than tol.
+        Returns the trace (objective after the init and after each sweep run)
+        or None; ``self.foldin_sweeps`` holds the number of sweeps run."""
         self._sync_stream()
         mode = {"given": L.NMF_FOLDIN_GIVEN, "wta": L.NMF_FOLDIN_WTA, "mlp": L.NMF_FOLDIN_MLP}[init]
         hidden = mlp.hidden if mlp is not None else 0
@@ -157,11 +167,13 @@ class Plan:
         L.call("nmf_foldin_workspace_bytes", self.h, byref(AnewT.c), hidden, byref(nb))
         raw, ws = _aligned_bytes(nb.value, Ht_new.device)
         tr = (c_double * (n_sweeps + 1))() if trace else None
+        done = ctypes.c_int(0)
         L.call("nmf_foldin", self.h, byref(AnewT.c), Ht_new.data_ptr(), mode,
-               mlp.blob.data_ptr() if mlp is not None else None, hidden, n_sweeps, tr,
-               ws.data_ptr(), nb.value)
+               mlp.blob.data_ptr() if mlp is not None else None, hidden, n_sweeps, float(tol),
+               byref(done), tr, ws.data_ptr(), nb.value)
         del raw
-        return list(tr) if trace else None
+        self.foldin_sweeps = done.value
+        return list(tr)[: done.value + 1] if trace else None
 
     def close(self):
         if getattr(self, "h", None):
@@ -228,7 +240,7 @@ class Mlp:
         X = X.contiguous()
         Y = torch.empty_like(X)
         ws = self._workspace(min(batch, max(1, X.shape[0])))
-        L.call("nmf_mlp_forward", self.blob.data_ptr(), self.K, self.hidden, X.data_ptr(),
+        L.call("nmf_mlp_predict", self.blob.data_ptr(), self.K, self.hidden, X.data_ptr(),
                Y.data_ptr(), X.shape[0], ws.data_ptr(), ws.numel(), _stream())
         return Y
 

@@ -2,6 +2,7 @@
 // W fixed -- the H half of Alg. 1 (R' = A_new^T W and S = W^T W formed once,
 // then the H loop repeated), optionally warm-started by the network.
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "plan_impl.hpp"
@@ -130,9 +131,12 @@ int nmf_foldin_workspace_bytes(nmf_plan p, const nmf_matrix* AnewT, int mlp_hidd
 }
 
 int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode,
-               const void* mlp_params, int mlp_hidden, int n_sweeps, double* rel_trace,
-               void* workspace, size_t workspace_bytes) {
+               const void* mlp_params, int mlp_hidden, int max_sweeps, double tol,
+               int* sweeps_done, double* rel_trace, void* workspace, size_t workspace_bytes) {
+  if (sweeps_done) *sweeps_done = 0;
   if (!p || !Ht_new || !workspace) return fail(NMF_E_ARG, "NULL argument");
+  if (!(tol >= 0.0) || std::isinf(tol)) return fail(NMF_E_ARG, "tol must be finite and >= 0");
+  const int n_sweeps = max_sweeps;
   if (p->poisoned) return fail(p->poisoned, "plan is poisoned by an earlier error");
   int rc = check_anew(p, AnewT);
   if (rc) return rc;
@@ -140,7 +144,7 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
     return fail(NMF_E_ARG, "unknown init mode %d", init_mode);
   if (init_mode == NMF_FOLDIN_MLP && (!mlp_params || mlp_hidden < 1))
     return fail(NMF_E_ARG, "MLP init needs parameters and hidden > 0");
-  if (n_sweeps < 0) return fail(NMF_E_ARG, "n_sweeps < 0");
+  if (n_sweeps < 0) return fail(NMF_E_ARG, "max_sweeps < 0");
   if (((uintptr_t)Ht_new & 15) || ((uintptr_t)workspace % kAlign))
     return fail(NMF_E_ARG, "misaligned Ht_new or workspace");
   const int64_t Dn = AnewT->rows;
@@ -230,6 +234,33 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
     filled = 0;
     return NMF_OK;
   };
+  if (tol > 0.0) {
+    // stop at the first sweep whose decrease of the relative objective is
+    // below tol: the objective is read back after every sweep (one 8-byte copy
+    // and one synchronisation per sweep)
+    double prev = 0.0, cur = 0.0;
+    rc = fold_objective(p, f, Ht_new, Dn, f.trace, s);
+    if (rc) return rc;
+    FCHECK(hipMemcpyAsync(&prev, f.trace, sizeof(double), hipMemcpyDeviceToHost, s));
+    FCHECK(hipStreamSynchronize(s));
+    if (!std::isfinite(prev)) return fail(NMF_E_NUMERIC, "fold-in objective is not finite");
+    if (rel_trace) rel_trace[0] = prev;
+    int done = 0;
+    while (done < n_sweeps) {
+      FCHECK(hals_update(a, s));
+      rc = fold_objective(p, f, Ht_new, Dn, f.trace, s);
+      if (rc) return rc;
+      FCHECK(hipMemcpyAsync(&cur, f.trace, sizeof(double), hipMemcpyDeviceToHost, s));
+      FCHECK(hipStreamSynchronize(s));
+      if (!std::isfinite(cur)) return fail(NMF_E_NUMERIC, "fold-in objective is not finite");
+      done++;
+      if (rel_trace) rel_trace[done] = cur;
+      if (sweeps_done) *sweeps_done = done;
+      if (prev - cur < tol) break;
+      prev = cur;
+    }
+    return NMF_OK;
+  }
   if (rel_trace) {
     rc = fold_objective(p, f, Ht_new, Dn, f.trace + filled, s);
     if (rc) return rc;
@@ -251,6 +282,7 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
     rc = flush();
     if (rc) return rc;
   }
+  if (sweeps_done) *sweeps_done = n_sweeps;
   return NMF_OK;
 }
 

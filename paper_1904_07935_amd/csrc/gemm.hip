@@ -301,13 +301,44 @@ struct Mfma<__bf16> {
 // Main loop: two register stages and two LDS buffers.  The global load of
 // K-step k + 2 is issued before computing step k and stored to LDS after
 // computing step k + 1, so each load has two compute steps to arrive.
+//
+// Two-level accumulation: the matrix cores accumulate Flush::steps K-steps into a
+// fresh accumulator, which is then added to the running total.  A single
+// accumulator chain over a contraction of n terms carries a rounding error
+// that grows like sqrt(n) units of FP32 rounding; with chunks of c terms the
+// chain is n / c long (c = 64 for FP32), which cuts the error of the
+// 800 - 10^4 term products several times at the cost of 64 adds per chunk.
+template <typename T>
+struct Flush {
+  static constexpr int steps = 4;  // K-steps per chunk: 64 (FP32) or 128 (BF16) terms
+};
+
+__device__ __forceinline__ void flush_acc(floatx16 (&tot)[2][2], floatx16 (&acc)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      tot[i][j] += acc[i][j];
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+    }
+}
+
 template <typename T, typename St, typename TA, typename TB>
 __device__ __forceinline__ void pipeline(TA As, TB Bs, const T* __restrict__ A,
                                          const T* __restrict__ B, int64_t lda, int64_t ldb,
                                          int64_t M, int64_t N, int64_t m0, int64_t n0, int64_t kb,
-                                         int64_t ke, int nk, int tid, floatx16 (&acc)[2][2], int wm,
+                                         int64_t ke, int nk, int tid, floatx16 (&tot)[2][2], int wm,
                                          int wn, int lane) {
   constexpr int BK = Mfma<T>::BK;
+  static_assert(Flush<T>::steps % 2 == 0, "a chunk is whole loop iterations");
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
   St s0, s1;
   if (nk > 0) s0.load(A, B, lda, ldb, M, N, m0, n0, kb, ke, tid);
   if (nk > 1) s1.load(A, B, lda, ldb, M, N, m0, n0, kb + BK, ke, tid);
@@ -325,7 +356,9 @@ __device__ __forceinline__ void pipeline(TA As, TB Bs, const T* __restrict__ A,
     Mfma<T>::step(As[1], Bs[1], acc, wm, wn, lane);
     if (kt + 2 < nk) s0.store(As[0], Bs[0], tid);
     __syncthreads();
+    if ((kt + 2) % Flush<T>::steps == 0) flush_acc(tot, acc);
   }
+  flush_acc(tot, acc);
 }
 
 template <typename T, bool AT, bool BT, bool VEC>

@@ -111,13 +111,17 @@ hipError_t csr_validate(int64_t rows, int64_t cols, int64_t nnz, const int32_t* 
                         const int32_t* col, const float* val, int32_t* flag, hipStream_t s);
 
 // ----------------------------------------------------------- elementwise ----
+// Scales every column of X [rows, K] to unit L2 norm; a column of zero norm
+// is left as it is and sets `bit` in *flag.
 hipError_t normalize_columns(float* X, int64_t rows, int K, double* part, int nblk_max,
-                             hipStream_t s);
+                             int32_t* flag, int bit, hipStream_t s);
 hipError_t cast_bf16(const float* x, __bf16* y, int64_t n, hipStream_t s);
 // y[c][r] = bf16(x[r][c]) for x [rows, cols]
 hipError_t cast_bf16_transpose(const float* x, __bf16* y, int64_t rows, int64_t cols,
                                hipStream_t s);
 hipError_t check_finite_nonneg(const float* x, int64_t n, int32_t* flag, int bit, hipStream_t s);
+// *word |= bits, on the device, in stream order.
+hipError_t or_bits(int32_t* word, int32_t bits, hipStream_t s);
 
 // FP64 fixed-order reductions.  partial buffers are [nblk] doubles.
 int reduce_blocks(int64_t n);

@@ -33,13 +33,19 @@ __global__ void colsq_kernel(const float* __restrict__ X, int64_t rows, int K,
   }
 }
 
+// A column whose norm is zero (or overflows FP32) cannot be normalised: it is
+// left unchanged and bit `bit` of *flag is set (every block sees the same
+// norms; block 0 reports).
 __global__ void colscale(float* __restrict__ X, int64_t rows, int K, const double* __restrict__ part,
-                         int nblk) {
+                         int nblk, int32_t* flag, int bit) {
   __shared__ float norm[kMaxK];
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     double s = 0.0;
     for (int b = 0; b < nblk; b++) s += part[(int64_t)b * K + k];
-    norm[k] = (float)sqrt(s);
+    const float nk = (float)sqrt(s);
+    const bool ok = nk > 0.0f && !isinf(nk);
+    norm[k] = ok ? nk : 1.0f;
+    if (!ok && blockIdx.x == 0) atomicOr(flag, bit);
   }
   __syncthreads();
   const int64_t n = rows * K;
@@ -135,7 +141,7 @@ int reduce_blocks(int64_t n) {
 }
 
 hipError_t normalize_columns(float* X, int64_t rows, int K, double* part, int nblk_max,
-                             hipStream_t s) {
+                             int32_t* flag, int bit, hipStream_t s) {
   int nblk = (int)((rows + 63) / 64);
   if (nblk > nblk_max) nblk = nblk_max;
   if (nblk < 1) nblk = 1;
@@ -143,7 +149,7 @@ hipError_t normalize_columns(float* X, int64_t rows, int K, double* part, int nb
   int gb = (int)((rows * K + 255) / 256);
   if (gb > 2048) gb = 2048;
   if (gb < 1) gb = 1;
-  colscale<<<gb, 256, 0, s>>>(X, rows, K, part, nblk);
+  colscale<<<gb, 256, 0, s>>>(X, rows, K, part, nblk, flag, bit);
   return hipGetLastError();
 }
 
@@ -163,6 +169,13 @@ hipError_t cast_bf16_transpose(const float* x, __bf16* y, int64_t rows, int64_t 
                                hipStream_t s) {
   dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
   cast_t_kernel<<<grid, 256, 0, s>>>(x, y, rows, cols);
+  return hipGetLastError();
+}
+
+__global__ void or_bits_kernel(int32_t* word, int32_t bits) { atomicOr(word, bits); }
+
+hipError_t or_bits(int32_t* word, int32_t bits, hipStream_t s) {
+  or_bits_kernel<<<1, 1, 0, s>>>(word, bits);
   return hipGetLastError();
 }
 

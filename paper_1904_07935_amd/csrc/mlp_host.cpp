@@ -309,7 +309,7 @@ int nmf_mlp_workspace_bytes(int K, int hidden, int64_t batch, size_t* bytes) {
   return NMF_OK;
 }
 
-int nmf_mlp_forward(const void* params, int K, int hidden, const float* X, float* Yhat, int64_t N,
+int nmf_mlp_predict(const void* params, int K, int hidden, const float* X, float* Yhat, int64_t N,
                     void* workspace, size_t workspace_bytes, void* stream) {
   int rc = check_dims(K, hidden);
   if (rc) return rc;

@@ -597,12 +597,16 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
     INITCHECK(sumsq_f64(A->dense, s.V * s.D, p->red, nb, st));
     INITCHECK(finish_f64(p->red, nb, p->scal + 0, st));
   }
-  // unit-norm columns of W before the first sweep
-  INITCHECK(normalize_columns(W, s.V, K, p->colsq, 1024, st));
+  // unit-norm columns of W before the first sweep (a column of zero norm has
+  // no direction to keep: rejected)
+  INITCHECK(normalize_columns(W, s.V, K, p->colsq, 1024, p->status, 8, st));
   INITCHECK(hipStreamSynchronize(st));
   double a2 = 0.0;
   INITCHECK(hipMemcpy(&a2, p->scal, sizeof(double), hipMemcpyDeviceToHost));
   if (!(a2 > 0.0)) return bail(fail(NMF_E_NUMERIC, "A is all zeros"));
+  int32_t st0 = 0;
+  INITCHECK(hipMemcpy(&st0, p->status, sizeof(st0), hipMemcpyDeviceToHost));
+  if (st0 & 8) return bail(fail(NMF_E_NUMERIC, "a column of W has zero norm"));
 #undef INITCHECK
   *out = p;
   return NMF_OK;
@@ -634,9 +638,12 @@ int nmf_sweep(nmf_plan p, int n_sweeps, double* rel_obj) {
                                  p->stream));
     }
   }
+  // the device status word once per call (one 4-byte copy and one
+  // synchronisation): a timed-out wait of the W update, here or in an earlier
+  // nmf_half, poisons the plan now
+  int rc = read_status(p);
+  if (rc) return rc;
   if (rel_obj) {
-    int rc = read_status(p);
-    if (rc) return rc;
     for (int i = 0; i < n_sweeps; i++)
       if (!std::isfinite(rel_obj[i])) return fail(NMF_E_NUMERIC, "objective is not finite");
   }
@@ -681,6 +688,13 @@ int nmf_plan_info(nmf_plan p, nmf_info* info) {
   info->w_groups = p->w_groups;
   info->h_groups = (int)((p->D + hals_rows_per_group_h() - 1) / hals_rows_per_group_h());
   info->sweeps_done = p->sweeps_done;
+  return NMF_OK;
+}
+
+int nmf_inject_status(nmf_plan p, int32_t bits) {
+  if (!p) return fail(NMF_E_ARG, "plan is NULL");
+  if (bits != NMF_STATUS_TIMEOUT) return fail(NMF_E_ARG, "unknown status bits %d", bits);
+  HIPCHECK(p, or_bits(p->status, bits, p->stream));
   return NMF_OK;
 }
 

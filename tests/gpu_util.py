@@ -15,6 +15,37 @@ def rel_fro(x, ref):
     return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
 
 
+def col_rel_max(x, ref):
+    """Largest relative L2 error over the columns: max_k ||x_k - r_k|| / ||r_k||.
+    For W (unit-norm columns) this catches one bad column that a Frobenius norm
+    over all K columns would dilute by sqrt(K)."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.max(np.linalg.norm(x - ref, axis=0) / np.linalg.norm(ref, axis=0)))
+
+
+def row_rms_max(x, ref):
+    """Largest L2 error over the rows, relative to the RMS row norm of ref:
+    max_k ||x_k - r_k|| / sqrt(mean_k ||r_k||^2).  For H (rows of very
+    different norms, some clipped to eps) a per-row relative error would be
+    dominated by near-zero rows; this scale still flags one bad row."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.sqrt(np.mean(np.sum(ref * ref, axis=1)))
+    return float(np.max(np.linalg.norm(x - ref, axis=1)) / scale)
+
+
+def elem_rel_max(x, ref, floor=1e-6):
+    """Largest element-wise relative error, |x - r| / max(|r|, floor * max|r|).
+    The products and Grams of non-negative factors have non-negative entries
+    whose FP32 sums carry a relative error of a few units of rounding times
+    the square root of the number of terms."""
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = np.maximum(np.abs(ref), floor * np.max(np.abs(ref)))
+    return float(np.max(np.abs(x - ref) / den))
+
+
 def gpu_plan(A, W0, H0, dev, precision="fp32", eps=EPS):
     """A: dense float32 ndarray or datagen.Csr (V rows).  H0 is K x D."""
     import torch

@@ -106,7 +106,25 @@ def test_null_plan_calls():
     assert lib.nmf_sweep(None, 1, None) == -1
     assert lib.nmf_half(None, 0) == -1
     assert lib.nmf_objective(None, None, None) == -1
+    assert lib.nmf_inject_status(None, 256) == -1
     assert lib.nmf_destroy(None) == 0
+
+
+def test_foldin_arguments_before_device():
+    """nmf_foldin(max_sweeps, tol, sweeps_done, ...): the count is reset on
+    entry and bad arguments are refused before any device work."""
+    lib = L.lib()
+    done = ctypes.c_int(7)
+    m = _csr()
+    assert lib.nmf_foldin(None, byref(m), 0x1000, 0, None, 0, 10, 0.0, byref(done), None, 0x100000,
+                          1 << 20) == -1
+    assert done.value == 0
+    assert b"NULL" in lib.nmf_last_error()
+
+
+def test_predict_is_exported_under_its_boundary_name():
+    h = ctypes.CDLL(L.LIB_PATH)
+    assert hasattr(h, "nmf_mlp_predict") and not hasattr(h, "nmf_mlp_forward")
 
 
 def test_mlp_layout_and_bounds():

@@ -1,22 +1,28 @@
 """BF16 product variant (error against the FP64 oracle stated, not bounded by
 the FP32 bar) and full-size configurations (MI355X only).
 
-Full-size parity compares one GPU sweep with one oracle sweep from the same
-FP32 inputs, in the launch configuration the benchmark times; where the
-oracle cannot afford the whole sweep (the 10^5 x 3*10^5 corpus) it checks the
-row-independent H half on sampled documents and properties that hold at any
-size."""
+Full-size parity runs the configurations at their stated sizes in the launch
+configuration the benchmark times and compares with the oracle from the same
+FP32 inputs: the 26,000 x 11,000 corpus for 10 sweeps at every rank, the dense
+10^4 x 10^4 problem for 5 sweeps, and on the 10^5 x 3*10^5 corpus one W half
+(every column against the oracle's) plus the row-independent H half on sampled
+documents and properties that hold at any size."""
 import numpy as np
 import pytest
 
 import datagen
 from oracle import hals
-from tests.gpu_util import (EPS, bf16_round, gpu_plan, oracle_A, oracle_run, rel_fro, small_bow,
-                            sparse_init)
+from tests.gpu_util import (EPS, bf16_round, col_rel_max, elem_rel_max, gpu_plan, oracle_A, oracle_run,
+                            rel_fro, row_rms_max, small_bow, sparse_init)
 
 pytestmark = pytest.mark.gpu
 
 BF16_REL_BOUND = 1e-2  # stated bound on |rel_bf16 - rel_fp64| / rel_fp64 at these sizes
+# FP32 against the FP64 oracle on the dense image-shaped problem after sweep 1:
+# a plain FP32 NumPy transcription of Alg. 1 differs by 3.9e-7, 7.8e-6, 2.2e-4,
+# 2.0e-4 and 6.1e-4 after sweeps 1-5 (rows of H clipped to eps in sweep 1 revive
+# at rounding level), so sweeps 2-5 are held to a bound of that order
+C2_FP32_LATER_BOUND = 1e-2
 
 
 def _np(t):
@@ -71,38 +77,123 @@ def test_bf16_products_sparse_error_stated(cuda, K):
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("K", [100, 200, 400])
-def test_c1_full_size_one_sweep(cuda, K):
-    """V = 26,000 x D = 11,000 CSR (the benchmark workload), one sweep."""
+def test_c1_full_size_10_sweeps(cuda, K):
+    """V = 26,000 x D = 11,000 CSR (the corpus stand-in), 10 sweeps: the
+    relative objective after every sweep within 1e-5 of the oracle's, and the
+    factors after sweep 10 within 1e-3 (Frobenius), per W column within 2e-3
+    and per H row within 1e-3 of the RMS row norm."""
     c = datagen.c1()
     W0, H0 = sparse_init(c, K)
     plan = gpu_plan(c.A, W0, H0, cuda)
-    rel = plan.sweep(1, objective=True)[0]
-    rel_or, facs = oracle_run(c.A, W0, H0, 1)
-    assert abs(rel - rel_or[0]) <= 1e-5 * rel_or[0]
-    assert rel_fro(_np(plan.W), facs[0][0]) <= 1e-3
-    assert rel_fro(_np(plan.Ht).T, facs[0][1]) <= 1e-3
+    rel = np.array(plan.sweep(10, objective=True))
+    print(f"C1 K={K}: GPU sweeps done; running the oracle", flush=True)
+    rel_or, facs = oracle_run(c.A, W0, H0, 10)
+    d = np.abs(rel - rel_or) / np.array(rel_or)
+    print(f"C1 K={K} relative objective difference per sweep:", np.array2string(d, precision=2))
+    assert d.max() <= 1e-5, d
+    Wg, Hg = _np(plan.W), _np(plan.Ht).T
+    Wo, Ho = facs[-1]
+    assert rel_fro(Wg, Wo) <= 1e-3 and rel_fro(Hg, Ho) <= 1e-3
+    assert col_rel_max(Wg, Wo) <= 2e-3
+    assert row_rms_max(Hg, Ho) <= 1e-3
+    plan.close()
+
+
+@pytest.mark.timeout(600)
+def test_c1_products_elementwise(cuda):
+    """The two sparse products and Grams of one sweep at full size (K = 200),
+    element by element against the oracle's products of the same factors."""
+    c = datagen.c1()
+    K = 200
+    W0, H0 = sparse_init(c, K)
+    plan = gpu_plan(c.A, W0, H0, cuda)
+    Ao = oracle_A(c.A)
+    Wn = _np(plan.W)
+    plan.half("H")
+    mid = plan.intermediates()
+    assert elem_rel_max(_np(mid["R"]), np.asarray(Ao.T @ Wn)) <= 1e-4
+    assert elem_rel_max(_np(mid["S"]), Wn.T @ Wn) <= 1e-4
+    Hn = _np(plan.Ht).T
+    plan.half("W")
+    mid = plan.intermediates()
+    P = np.asarray(Ao @ Hn.T)
+    assert elem_rel_max(_np(mid["P"]), P) <= 1e-4
+    assert np.all(_np(mid["P"])[np.diff(c.A.rowptr) == 0] == 0.0)
+    assert elem_rel_max(_np(mid["Q"]), Hn @ Hn.T) <= 1e-4
     plan.close()
 
 
 @pytest.mark.timeout(900)
-def test_c2_full_size_one_sweep(cuda):
-    """Dense 10^4 x 10^4 image-shaped matrix, K = 240: FP32 parity and the BF16
-    error stated after one sweep."""
+def test_c2_full_size_5_sweeps(cuda):
+    """Dense 10^4 x 10^4 image-shaped matrix, K = 240, from the configuration's
+    plain U[0,1) init, 5 sweeps: the FP32 path against the oracle after every
+    sweep, and the BF16-product path's error against the oracle stated per
+    sweep.  This init clips most rows of H to eps in the first sweep (dead
+    components whose revival is decided at rounding level), so the 1e-5 bar
+    holds for the first sweep; later sweeps are held to the bound a plain FP32
+    transcription of Alg. 1 also meets on this problem."""
     A = datagen.c2()
     W0, H0 = datagen.uniform_init(10000, 10000, 240, seed=1)
     plan = gpu_plan(A, W0, H0, cuda)
-    rel = plan.sweep(1, objective=True)[0]
+    r32 = np.array(plan.sweep(5, objective=True))
     plan.close()
     p16 = gpu_plan(A, W0, H0, cuda, precision="bf16")
-    rel16 = p16.sweep(1, objective=True)[0]
+    r16 = np.array(p16.sweep(5, objective=True))
     p16.close()
-    Ao = A.astype(np.float64)
-    W = hals.normalize_columns(W0)
-    W, H = hals.sweep(Ao, W, H0.astype(np.float64), EPS)
-    _, rel_or = hals.objective(Ao, W, H)
-    print(f"C2 one sweep: fp32 {rel:.8f} bf16 {rel16:.8f} oracle {rel_or:.8f}")
-    assert abs(rel - rel_or) <= 1e-5 * rel_or
-    assert abs(rel16 - rel_or) <= BF16_REL_BOUND * rel_or
+    print("C2: GPU sweeps done; running the oracle", flush=True)
+    rel_or, _ = oracle_run(A, W0, H0, 5)
+    rel_or = np.array(rel_or)
+    e32 = np.abs(r32 - rel_or) / rel_or
+    e16 = np.abs(r16 - rel_or) / rel_or
+    print("C2 fp32 rel-objective error per sweep:", np.array2string(e32, precision=2))
+    print("C2 bf16 rel-objective error per sweep:", np.array2string(e16, precision=2))
+    assert e32[0] <= 1e-5
+    assert e32.max() <= C2_FP32_LATER_BOUND
+    assert e16.max() <= BF16_REL_BOUND
+    assert np.all(np.isfinite(r16))
+
+
+@pytest.mark.timeout(900)
+def test_c4_w_half_matches_oracle(cuda):
+    """10^5 x 3*10^5 CSR, K = 400 (56 column groups spread over XCDs: the
+    device-scope norm exchange, four rows per thread): one W half from the
+    initial factors, every column against the oracle's W half (P and Q formed
+    by the oracle)."""
+    c = datagen.c4()
+    K = 400
+    W0, H0 = sparse_init(c, K)
+    plan = gpu_plan(c.A, W0, H0, cuda)
+    assert plan.info()["w_groups"] > 32
+    plan.half("W")
+    Wg = _np(plan.W)
+    plan.close()
+    print("C4: GPU W half done; running the oracle", flush=True)
+    Wo, _, _ = hals.w_half(oracle_A(c.A), hals.normalize_columns(W0), np.asarray(H0, np.float64), EPS)
+    print(f"C4 W half: fro {rel_fro(Wg, Wo):.2e}, worst column {col_rel_max(Wg, Wo):.2e}")
+    assert rel_fro(Wg, Wo) <= 5e-4
+    assert col_rel_max(Wg, Wo) <= 1e-3
+
+
+@pytest.mark.timeout(600)
+def test_c1_plain_uniform_init_properties(cuda):
+    """The corpus configuration's own init (plain U[0,1) for W and H, not the
+    scale-matched H): what Alg. 1 guarantees at any precision holds -- finite,
+    H >= eps, W > 0 with unit columns, objective non-increasing -- and the
+    difference from the oracle's trajectory is stated."""
+    c = datagen.c1()
+    K = 100
+    W0, H0 = datagen.uniform_init(c.A.rows, c.A.cols, K, seed=1)
+    plan = gpu_plan(c.A, W0, H0, cuda)
+    rel = np.array(plan.sweep(5, objective=True))
+    Wg, Hg = _np(plan.W), _np(plan.Ht)
+    assert np.all(np.isfinite(Wg)) and np.all(np.isfinite(Hg))
+    assert Hg.min() >= EPS * (1 - 1e-6) and Wg.min() > 0
+    np.testing.assert_allclose(np.linalg.norm(Wg, axis=0), 1.0, rtol=1e-5)
+    assert np.all(np.diff(rel) <= 1e-6 * rel[1:])
+    rel_or, _ = oracle_run(c.A, W0, H0, 5)
+    print("C1 plain init: |rel - rel_oracle| / rel_oracle per sweep:",
+          np.array2string(np.abs(rel - rel_or) / np.array(rel_or), precision=2))
+    plan.close()
 
 
 @pytest.mark.timeout(900)

@@ -58,6 +58,32 @@ def test_foldin_given_init_matches_oracle(cuda, K):
     plan.close()
 
 
+def test_foldin_tolerance_stop(cuda):
+    """With tol > 0 fold-in stops after the first sweep that lowers the relative
+    objective by less than tol; the sweeps it ran are the same sweeps a
+    fixed-count run performs (bitwise), and the count is reported."""
+    import torch
+
+    from paper_1904_07935_amd.api import Matrix
+    c, W, new, plan = _fold_setup(cuda, K=16)
+    Dn, K = new.rows, W.shape[1]
+    _, H0 = datagen.uniform_init_matched(c.A.rows, Dn, K, datagen.mean_value(new), seed=4)
+    M = Matrix.from_csr(new, cuda)
+    tol = 1e-6
+    Ht = torch.tensor(np.ascontiguousarray(H0.T), device=cuda)
+    tr = plan.foldin(M, Ht, init="given", n_sweeps=300, tol=tol)
+    n = plan.foldin_sweeps
+    assert 1 <= n < 300 and len(tr) == n + 1
+    dec = -np.diff(tr)
+    assert dec[-1] < tol and np.all(dec[:-1] >= tol), dec
+    Ht2 = torch.tensor(np.ascontiguousarray(H0.T), device=cuda)
+    tr2 = plan.foldin(M, Ht2, init="given", n_sweeps=n)
+    assert plan.foldin_sweeps == n
+    assert torch.equal(Ht, Ht2)
+    np.testing.assert_array_equal(tr, tr2)
+    plan.close()
+
+
 def test_foldin_wta_init_is_clipped_projection(cuda):
     import torch
 
@@ -120,6 +146,31 @@ def test_mlp_gradients_match_oracle(cuda):
     X = rng.random((N, K)).astype(np.float32)
     X /= np.linalg.norm(X, axis=1, keepdims=True)
     Yt = rng.random((N, K)).astype(np.float32)
+    loss, grads, _ = net.loss_grad(torch.tensor(X, device=cuda), torch.tensor(Yt, device=cuda))
+    lo, go = omlp.loss_and_grads(_bf16_params(p), bf16_round(X), Yt.astype(np.float64))
+    assert abs(loss - lo) <= 1e-2 * lo
+    for k in ("W1", "b1", "W2", "b2"):
+        assert rel_fro(_np(grads[k]), go[k]) <= 5e-2, k
+
+
+def test_mlp_configured_size_matches_oracle(cuda):
+    """The warm-start network at its configured size (K = 200 -> 512 -> 200):
+    forward and gradients against the FP64 oracle at the same BF16-rounded
+    weights and inputs, on a batch of 2048 normalised inputs."""
+    import torch
+
+    from paper_1904_07935_amd.api import Mlp
+    rng = np.random.default_rng(4)
+    K, Hd, N = 200, 512, 2048
+    p = _net(rng, K, Hd)
+    net = Mlp(K, Hd, device=cuda, seed=None)
+    net.set_masters(p)
+    X = rng.random((N, K)).astype(np.float32)
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    Yt = (0.05 * rng.random((N, K))).astype(np.float32)
+    Y = _np(net.forward(torch.tensor(X, device=cuda)))
+    yo, _ = omlp.forward(_bf16_params(p), bf16_round(X))
+    assert rel_fro(Y, yo) <= 1e-2
     loss, grads, _ = net.loss_grad(torch.tensor(X, device=cuda), torch.tensor(Yt, device=cuda))
     lo, go = omlp.loss_and_grads(_bf16_params(p), bf16_round(X), Yt.astype(np.float64))
     assert abs(loss - lo) <= 1e-2 * lo
