@@ -198,6 +198,26 @@ int nmf_foldin(nmf_plan plan, const nmf_matrix* AnewT, float* Ht_new, int init_m
                const void* mlp_params, int mlp_hidden, int max_sweeps, double tol,
                int* sweeps_done, double* rel_trace, void* workspace, size_t workspace_bytes);
 
+/* nmf_foldin without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  The workspace is a device array owned by the library:
+ * NMF_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, reserved when the library's code
+ * is loaded on that GPU and held until the process ends; its address is looked
+ * up on the first call on each device.  Arguments, results and errors are those
+ * of nmf_foldin, plus:
+ *   NMF_E_WORKSPACE  nmf_foldin_workspace_bytes() for these documents exceeds
+ *                    NMF_NOALLOC_SCRATCH_BYTES (fold the documents in smaller
+ *                    batches, or call nmf_foldin);
+ *   NMF_E_ARG        the current device is not the plan's.
+ * The call allocates no device memory.  Every call on a GPU uses the same
+ * array and leaves its contents behind (each call clears what it needs
+ * zeroed): calls that overlap on one GPU -- on different streams, or from
+ * different host threads -- race and give unspecified results.             */
+#define NMF_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int nmf_foldin_noalloc(nmf_plan plan, const nmf_matrix* AnewT, float* Ht_new, int init_mode,
+                       const void* mlp_params, int mlp_hidden, int max_sweeps, double tol,
+                       int* sweeps_done, double* rel_trace);
+
 /* ------------------------------------------------- warm-start network ----
  * y = softplus(W2 GELU(W1 x + b1) + b2), x in R^K, hidden units `hidden`
  * (GELU erf form; softplus(z) = z for z > 20).  Parameter blob (device, caller

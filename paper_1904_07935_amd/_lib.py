@@ -68,6 +68,8 @@ SIGNATURES = {
     "nmf_foldin_workspace_bytes": [_P, POINTER(nmf_matrix), c_int, POINTER(c_size_t)],
     "nmf_foldin": [_P, POINTER(nmf_matrix), _P, c_int, _P, c_int, c_int, c_double, POINTER(c_int),
                    POINTER(c_double), _P, c_size_t],
+    "nmf_foldin_noalloc": [_P, POINTER(nmf_matrix), _P, c_int, _P, c_int, c_int, c_double,
+                           POINTER(c_int), POINTER(c_double)],
     "nmf_mlp_param_bytes": [c_int, c_int, POINTER(nmf_mlp_layout)],
     "nmf_mlp_init": [_P, c_int, c_int, c_uint64, _P],
     "nmf_mlp_refresh": [_P, c_int, c_int, _P],

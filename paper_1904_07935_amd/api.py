@@ -153,25 +153,31 @@ class Plan:
         return {f: getattr(i, f) for f, _ in L.nmf_info._fields_}
 
     def foldin(self, AnewT: Matrix, Ht_new: torch.Tensor, init="given", mlp=None, n_sweeps=10,
-               trace=True, tol=0.0):
+               trace=True, tol=0.0, noalloc=False):
         """H-only sweeps for new documents (rows of AnewT) with this plan's W fixed.
 
         ``n_sweeps`` is the most sweeps run; with ``tol > 0`` the call stops
         after the first sweep lowering the relative objective by less than tol.
+        ``noalloc=True`` calls nmf_foldin_noalloc (the library's own device
+        array as workspace) instead of allocating one here.
         Returns the trace (objective after the init and after each sweep run)
         or None; ``self.foldin_sweeps`` holds the number of sweeps run."""
         self._sync_stream()
         mode = {"given": L.NMF_FOLDIN_GIVEN, "wta": L.NMF_FOLDIN_WTA, "mlp": L.NMF_FOLDIN_MLP}[init]
         hidden = mlp.hidden if mlp is not None else 0
-        nb = c_size_t(0)
-        L.call("nmf_foldin_workspace_bytes", self.h, byref(AnewT.c), hidden, byref(nb))
-        raw, ws = _aligned_bytes(nb.value, Ht_new.device)
+        params = mlp.blob.data_ptr() if mlp is not None else None
         tr = (c_double * (n_sweeps + 1))() if trace else None
         done = ctypes.c_int(0)
-        L.call("nmf_foldin", self.h, byref(AnewT.c), Ht_new.data_ptr(), mode,
-               mlp.blob.data_ptr() if mlp is not None else None, hidden, n_sweeps, float(tol),
-               byref(done), tr, ws.data_ptr(), nb.value)
-        del raw
+        if noalloc:
+            L.call("nmf_foldin_noalloc", self.h, byref(AnewT.c), Ht_new.data_ptr(), mode, params,
+                   hidden, n_sweeps, float(tol), byref(done), tr)
+        else:
+            nb = c_size_t(0)
+            L.call("nmf_foldin_workspace_bytes", self.h, byref(AnewT.c), hidden, byref(nb))
+            raw, ws = _aligned_bytes(nb.value, Ht_new.device)
+            L.call("nmf_foldin", self.h, byref(AnewT.c), Ht_new.data_ptr(), mode, params, hidden,
+                   n_sweeps, float(tol), byref(done), tr, ws.data_ptr(), nb.value)
+            del raw
         self.foldin_sweeps = done.value
         return list(tr)[: done.value + 1] if trace else None
 

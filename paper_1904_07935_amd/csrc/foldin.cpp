@@ -133,6 +133,18 @@ int nmf_foldin_workspace_bytes(nmf_plan p, const nmf_matrix* AnewT, int mlp_hidd
 int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode,
                const void* mlp_params, int mlp_hidden, int max_sweeps, double tol,
                int* sweeps_done, double* rel_trace, void* workspace, size_t workspace_bytes) {
+  return foldin_run(p, AnewT, Ht_new, init_mode, mlp_params, mlp_hidden, max_sweeps, tol,
+                    sweeps_done, rel_trace, workspace, workspace_bytes);
+}
+
+}  // extern "C"
+
+// The body of nmf_foldin, shared with the entry point whose workspace is the
+// library's own device array.
+int plnmf::foldin_run(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode,
+                      const void* mlp_params, int mlp_hidden, int max_sweeps, double tol,
+                      int* sweeps_done, double* rel_trace, void* workspace,
+                      size_t workspace_bytes) {
   if (sweeps_done) *sweeps_done = 0;
   if (!p || !Ht_new || !workspace) return fail(NMF_E_ARG, "NULL argument");
   if (!(tol >= 0.0) || std::isinf(tol)) return fail(NMF_E_ARG, "tol must be finite and >= 0");
@@ -285,5 +297,3 @@ int nmf_foldin(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode
   if (sweeps_done) *sweeps_done = n_sweeps;
   return NMF_OK;
 }
-
-}  // extern "C"

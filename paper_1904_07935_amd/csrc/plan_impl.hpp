@@ -104,4 +104,8 @@ namespace plnmf {
 // (p->panel) with that diagonal rule
 hipError_t gram(nmf_plan_s* p, const float* X, int64_t rows, float* out, int panel_diag = -1);
 int enqueue_objective(nmf_plan_s* p);
+// nmf_foldin on a given workspace (also serves the entry point that brings none)
+int foldin_run(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode,
+               const void* mlp_params, int mlp_hidden, int max_sweeps, double tol,
+               int* sweeps_done, double* rel_trace, void* workspace, size_t workspace_bytes);
 }  // namespace plnmf
