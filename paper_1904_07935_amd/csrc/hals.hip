@@ -425,6 +425,265 @@ __global__ __launch_bounds__(256) void hals_h_kernel(HalsArgs a) {
   }
 }
 
+hipError_t allow_smem(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Rows-in-registers variant for many rows (large D).  A workgroup is four
+// waves, each owning 32 rows that stay in VGPRs for the whole sweep, laid out
+// as the A operand of the 32x32x2 FP32 matrix-core product: lane (m, h) holds
+// X[row m][32 t + 2 s + h] in xa[16 t + s].  Per tile every wave forms its
+// rows' whole-contraction product itself, with the B operand (the tile's
+// panel) read from LDS, where the workgroup stages it one tile ahead in the
+// order the lanes read it (16-byte reads, no bank conflicts).  Phase 2 runs on
+// all 64 lanes in the same layout: lane (m, h) keeps row m's tile columns of
+// parity h, and at each column step the lane pair exchanges the clipped value
+// with one cross-half lane swap (v_permlane32_swap), so every lane does half
+// of the row's updates and the finished values already sit where xa wants
+// them.  Compared with the LDS-resident kernel, which holds 32 rows and a
+// panel per workgroup, four times as many rows share one panel and every
+// SIMD runs its own wave's product and phase 2.
+// LDS (floats): panel [2][32 NT][32] | gh [2][2][T][16] | part [4][32][TP].
+constexpr int kRowsRR = 32;    // rows per wave
+constexpr int kWavesRR = 4;    // waves per workgroup
+__host__ __device__ inline size_t rr_smem_floats(int NT) {
+  return 2 * (size_t)NT * 1024 + 2 * 2 * T * 16 + kWavesRR * 32 * TP;
+}
+
+// Stage tile j's panel (kpad(K) rows of 32, then zeros up to 32 NT rows) and
+// its G block: all threads; the panel in lane-read order
+// ((t * 4 + q) * 2 + h) * 32 + m float4s, holding rows 32 t + 2 (4 q + i) + h;
+// the G block split by column parity, gh[h][t][k] = G[t][2 k + h] for
+// 2 k + h > t and 0 otherwise (the columns a step updates).
+template <int NT>
+__device__ __forceinline__ void rr_stage(const float* __restrict__ panel, const float* __restrict__ gblk,
+                                         int kp, int j, float* lp, float* gt, int tid) {
+  const floatx4* src = (const floatx4*)(panel + (int64_t)j * kp * T);
+  constexpr int N4 = NT * 32 * 8;  // float4s of 32 NT rows
+#pragma unroll
+  for (int k = 0; k < (N4 + 255) / 256; k++) {
+    const int i = tid + 256 * k;
+    if (i < N4) {
+      const int l = i >> 3, c0 = 4 * (i & 7);
+      const floatx4 v = l < kp ? src[i] : floatx4{0, 0, 0, 0};
+      const int t = l >> 5, r = l & 31, s2 = r >> 1, h = r & 1, q = s2 >> 2, ii = s2 & 3;
+      float* d = lp + ((((t * 4 + q) * 2 + h) * 32 + c0) * 4) + ii;
+      d[0] = v[0];
+      d[4] = v[1];
+      d[8] = v[2];
+      d[12] = v[3];
+    }
+  }
+  const float* gs = gblk + (int64_t)j * T * T;
+  {
+    const int idx = 4 * tid, h = idx >> 9, t = (idx >> 4) & 31, k0 = idx & 15;
+    floatx4 v;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int c = 2 * (k0 + e) + h;
+      v[e] = c > t ? gs[t * T + c] : 0.0f;
+    }
+    *(floatx4*)(gt + idx) = v;
+  }
+}
+
+template <int NT, bool VEC>
+__global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
+  extern __shared__ float smem_raw[];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 31, h = lane >> 5;
+  const int K = a.K, kp = kpad(K), ntiles = (K + T - 1) / T;
+  float* lpb = smem_raw;                 // [2][NT * 1024]
+  float* gtb = lpb + 2 * NT * 1024;      // [2][2 * T * 16]
+  float* part = gtb + 2 * 2 * T * 16 + w * 32 * TP;
+  const int64_t row0 = ((int64_t)blockIdx.x * kWavesRR + w) * kRowsRR;
+  const int nr = a.rows - row0 < kRowsRR ? (int)(a.rows - row0) : kRowsRR;  // may be <= 0
+  const float eps = a.eps;
+  float* __restrict__ X = a.X;
+
+  rr_stage<NT>(a.panel, a.gblk, kp, 0, lpb, gtb, tid);
+  // the wave's rows into the A-operand layout, one 32-column tile at a time
+  float xa[16 * NT];
+#pragma unroll
+  for (int t = 0; t < NT; t++) {
+    if (lane < kRowsRR) {
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        const int c = 32 * t + 4 * q;
+        floatx4 v = floatx4{0, 0, 0, 0};
+        if (lane < nr) {
+          const float* src = X + (row0 + lane) * K + c;
+          if constexpr (VEC) {
+            if (c < K) v = *(const floatx4*)src;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+              if (c + e < K) v[e] = src[e];
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; e++) part[lane * TP + 4 * q + e] = v[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < 16; s2++) xa[16 * t + s2] = part[m * TP + 2 * s2 + h];
+    __syncthreads();
+  }
+
+#pragma unroll 1
+  for (int j = 0; j < ntiles; j++) {
+    const int a0 = j * T, tw = a0 + T < K ? T : K - a0;
+    const float* lp = lpb + (j & 1) * NT * 1024;
+    const float* gt = gtb + (j & 1) * 2 * T * 16;
+    // Bterm of the tile in the product's lane layout
+    float bt[16];
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int rl = 8 * jj + 4 * h + i;
+        bt[4 * jj + i] = (rl < nr && m < tw) ? a.Bterm[(row0 + rl) * K + a0 + m] : 0.0f;
+      }
+    // the tile product over the whole contraction, B operand from LDS
+    floatx16 acc;
+#pragma unroll
+    for (int e = 0; e < 16; e++) acc[e] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const floatx4 b = *(const floatx4*)(lp + (((t * 4 + q) * 2 + h) * 32 + m) * 4);
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[16 * t + 4 * q + i], b[i], acc, 0, 0, 0);
+      }
+    }
+    // the next tile's panel into the other buffer (its last readers finished
+    // before the barrier that ended the previous tile)
+    if (j + 1 < ntiles)
+      rr_stage<NT>(a.panel, a.gblk, kp, j + 1, lpb + ((j + 1) & 1) * NT * 1024,
+                   gtb + ((j + 1) & 1) * 2 * T * 16, tid);
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) part[(8 * jj + 4 * h + i) * TP + m] = acc[4 * jj + i] + bt[4 * jj + i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // phase 2 on all lanes: lane (m, h) holds row m's columns 2 k + h
+    float yh[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) yh[k] = part[m * TP + 2 * k + h];
+    {
+      const float* gp = gt + h * T * 16;
+      float gc[16], gn[16];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const floatx4 v = *(const floatx4*)(gp + 4 * q);
+#pragma unroll
+        for (int e = 0; e < 4; e++) gc[4 * q + e] = v[e];
+      }
+#pragma unroll
+      for (int t = 0; t < T; t++) {
+        const int u = t >> 1;
+        if (t + 1 < T) {  // step t + 1's G row, loaded during step t
+#pragma unroll
+          for (int q = ((t + 1) >> 1) >> 2; q < 4; q++) {
+            const floatx4 v = *(const floatx4*)(gp + (t + 1) * 16 + 4 * q);
+#pragma unroll
+            for (int e = 0; e < 4; e++) gn[4 * q + e] = v[e];
+          }
+        }
+        asm volatile("" ::: "memory");
+        // column t lives in the lanes of parity t & 1: clip there, then one
+        // swap gives both halves the clipped value
+        const float cand = fmaxf(eps, yh[u]);
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(cand), __float_as_uint(cand),
+                                                         false, false);
+        const float x = __uint_as_float((t & 1) ? sw[1] : sw[0]);
+        yh[u] = h == (t & 1) ? x : yh[u];
+#pragma unroll
+        for (int k = u; k < 16; k++) yh[k] -= x * gc[k];  // gc is 0 for columns <= t
+#pragma unroll
+        for (int k = (t + 1) >> 1; k < 16; k++) gc[k] = gn[k];
+      }
+    }
+    if (tw < T) {
+#pragma unroll
+      for (int k = 0; k < 16; k++)
+        if (2 * k + h >= tw) yh[k] = 0.0f;
+    }
+    // the new tile values: into xa, and through part to the rows in global memory
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+      if (t == j) {  // uniform: one branch per tile, no copy of xa
+#pragma unroll
+        for (int k = 0; k < 16; k++) xa[16 * t + k] = yh[k];
+      }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int k = 0; k < 16; k++) part[m * TP + 2 * k + h] = yh[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+      const int rl = lane >> 1, c0 = 16 * (lane & 1);  // row rl, columns c0 .. c0 + 15
+      if (rl < nr) {
+        float* dst = X + (row0 + rl) * K + a0 + c0;
+        const float* sp = part + rl * TP + c0;
+        if (VEC && tw == T) {
+#pragma unroll
+          for (int q = 0; q < 4; q++)
+            *(floatx4*)(dst + 4 * q) = floatx4{sp[4 * q], sp[4 * q + 1], sp[4 * q + 2], sp[4 * q + 3]};
+        } else {
+#pragma unroll
+          for (int c = 0; c < 16; c++)
+            if (c0 + c < tw) dst[c] = sp[c];
+        }
+      }
+    }
+    // every wave is done with this tile's panel and part; the next panel is staged
+    __syncthreads();
+  }
+}
+
+template <int NT>
+hipError_t launch_h_rows(const HalsArgs& b, bool vec, hipStream_t s) {
+  const unsigned grid = (unsigned)((b.rows + kWavesRR * kRowsRR - 1) / (kWavesRR * kRowsRR));
+  const size_t bytes = rr_smem_floats(NT) * 4;
+  const void* fn = vec ? (const void*)hals_h_rows_kernel<NT, true> : (const void*)hals_h_rows_kernel<NT, false>;
+  hipError_t e = allow_smem(fn, bytes);
+  if (e != hipSuccess) return e;
+  if (vec) hals_h_rows_kernel<NT, true><<<grid, 256, bytes, s>>>(b);
+  else hals_h_rows_kernel<NT, false><<<grid, 256, bytes, s>>>(b);
+  return hipGetLastError();
+}
+
+hipError_t h_rows_dispatch(const HalsArgs& b, bool vec, hipStream_t s) {
+  switch ((b.K + T - 1) / T) {
+    case 1: return launch_h_rows<1>(b, vec, s);
+    case 2: return launch_h_rows<2>(b, vec, s);
+    case 3: return launch_h_rows<3>(b, vec, s);
+    case 4: return launch_h_rows<4>(b, vec, s);
+    case 5: return launch_h_rows<5>(b, vec, s);
+    case 6: return launch_h_rows<6>(b, vec, s);
+    case 7: return launch_h_rows<7>(b, vec, s);
+    case 8: return launch_h_rows<8>(b, vec, s);
+    case 9: return launch_h_rows<9>(b, vec, s);
+    case 10: return launch_h_rows<10>(b, vec, s);
+    case 11: return launch_h_rows<11>(b, vec, s);
+    case 12: return launch_h_rows<12>(b, vec, s);
+    case 13: return launch_h_rows<13>(b, vec, s);
+    case 14: return launch_h_rows<14>(b, vec, s);
+    case 15: return launch_h_rows<15>(b, vec, s);
+    case 16: return launch_h_rows<16>(b, vec, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ---------------------------------------------------------------- W half ----
 
 constexpr int kWThreads = 512;
@@ -954,14 +1213,23 @@ const void* w_kernel_for(int rpt, bool vec, bool local) {
   return local ? w_kernel_for_t<true>(rpt, vec) : w_kernel_for_t<false>(rpt, vec);
 }
 
-hipError_t allow_smem(const void* fn, size_t bytes) {
-  if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
 
 }  // namespace
 
 int hals_rows_per_group_h() { return kRowsH; }
+
+// Which H-update kernel.  The rows-in-registers kernel takes 128 rows per
+// workgroup and fills the chip from about 256 x 128 rows on; below that the
+// LDS-resident kernel (32 rows per workgroup) keeps more CUs busy.
+// NMF_H_KERNEL=rows|lds forces one (read at every call: measurement, tests).
+static bool h_rows_kernel_for(int64_t rows, int K) {
+  (void)K;
+  if (const char* e = getenv("NMF_H_KERNEL")) {
+    if (e[0] == 'r') return true;
+    if (e[0] == 'l') return false;
+  }
+  return rows >= 32768;
+}
 
 size_t hals_panel_floats(int K) {
   const int ntiles = (K + T - 1) / T;
@@ -975,6 +1243,7 @@ hipError_t hals_update(const HalsArgs& a, hipStream_t s) {
   HalsArgs b = a;
   b.gblk = a.panel + (int64_t)((a.K + T - 1) / T) * kpad(a.K) * T;
   const bool vec = (a.K % 4 == 0) && (((uintptr_t)a.X & 15) == 0);
+  if (h_rows_kernel_for(a.rows, a.K)) return h_rows_dispatch(b, vec, s);
   const size_t bytes = h_smem_floats(a.K) * 4;
   const void* fn = vec ? (const void*)hals_h_kernel<true> : (const void*)hals_h_kernel<false>;
   hipError_t e = allow_smem(fn, bytes);
