@@ -457,35 +457,44 @@ __host__ __device__ inline size_t rr_smem_floats(int NT) {
 // the G block split by column parity, gh[h][t][k] = G[t][2 k + h] for
 // 2 k + h > t and 0 otherwise (the columns a step updates).
 template <int NT>
-__device__ __forceinline__ void rr_stage(const float* __restrict__ panel, const float* __restrict__ gblk,
-                                         int kp, int j, float* lp, float* gt, int tid) {
+struct RrStage {
+  floatx4 v[NT];  // thread tid's float4s tid + 256 k of the panel
+  floatx4 g;      // its four G-block entries
+};
+
+// Global loads of tile j's staging (issued early, stored by rr_store).
+template <int NT>
+__device__ __forceinline__ void rr_load(const float* __restrict__ panel, const float* __restrict__ gblk,
+                                        int kp, int j, int tid, RrStage<NT>& st) {
   const floatx4* src = (const floatx4*)(panel + (int64_t)j * kp * T);
-  constexpr int N4 = NT * 32 * 8;  // float4s of 32 NT rows
 #pragma unroll
-  for (int k = 0; k < (N4 + 255) / 256; k++) {
-    const int i = tid + 256 * k;
-    if (i < N4) {
-      const int l = i >> 3, c0 = 4 * (i & 7);
-      const floatx4 v = l < kp ? src[i] : floatx4{0, 0, 0, 0};
-      const int t = l >> 5, r = l & 31, s2 = r >> 1, h = r & 1, q = s2 >> 2, ii = s2 & 3;
-      float* d = lp + ((((t * 4 + q) * 2 + h) * 32 + c0) * 4) + ii;
-      d[0] = v[0];
-      d[4] = v[1];
-      d[8] = v[2];
-      d[12] = v[3];
-    }
+  for (int k = 0; k < NT; k++) {
+    const int i = tid + 256 * k, l = i >> 3;
+    st.v[k] = l < kp ? src[i] : floatx4{0, 0, 0, 0};
   }
   const float* gs = gblk + (int64_t)j * T * T;
-  {
-    const int idx = 4 * tid, h = idx >> 9, t = (idx >> 4) & 31, k0 = idx & 15;
-    floatx4 v;
+  const int idx = 4 * tid, h = idx >> 9, t = (idx >> 4) & 31, k0 = idx & 15;
 #pragma unroll
-    for (int e = 0; e < 4; e++) {
-      const int c = 2 * (k0 + e) + h;
-      v[e] = c > t ? gs[t * T + c] : 0.0f;
-    }
-    *(floatx4*)(gt + idx) = v;
+  for (int e = 0; e < 4; e++) {
+    const int c = 2 * (k0 + e) + h;
+    st.g[e] = c > t ? gs[t * T + c] : 0.0f;
   }
+}
+
+template <int NT>
+__device__ __forceinline__ void rr_store(const RrStage<NT>& st, float* lp, float* gt, int tid) {
+#pragma unroll
+  for (int k = 0; k < NT; k++) {
+    const int i = tid + 256 * k;
+    const int l = i >> 3, c0 = 4 * (i & 7);
+    const int t = l >> 5, r = l & 31, s2 = r >> 1, h = r & 1, q = s2 >> 2, ii = s2 & 3;
+    float* d = lp + ((((t * 4 + q) * 2 + h) * 32 + c0) * 4) + ii;
+    d[0] = st.v[k][0];
+    d[4] = st.v[k][1];
+    d[8] = st.v[k][2];
+    d[12] = st.v[k][3];
+  }
+  *(floatx4*)(gt + 4 * tid) = st.g;
 }
 
 template <int NT, bool VEC>
@@ -501,7 +510,11 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
   const float eps = a.eps;
   float* __restrict__ X = a.X;
 
-  rr_stage<NT>(a.panel, a.gblk, kp, 0, lpb, gtb, tid);
+  {
+    RrStage<NT> st;
+    rr_load<NT>(a.panel, a.gblk, kp, 0, tid, st);
+    rr_store<NT>(st, lpb, gtb, tid);
+  }
   // the wave's rows into the A-operand layout, one 32-column tile at a time
   float xa[16 * NT];
 #pragma unroll
@@ -545,6 +558,9 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
         const int rl = 8 * jj + 4 * h + i;
         bt[4 * jj + i] = (rl < nr && m < tw) ? a.Bterm[(row0 + rl) * K + a0 + m] : 0.0f;
       }
+    // the next tile's staging: global loads now, LDS stores after the product
+    RrStage<NT> st;
+    if (j + 1 < ntiles) rr_load<NT>(a.panel, a.gblk, kp, j + 1, tid, st);
     // the tile product over the whole contraction, B operand from LDS
     floatx16 acc;
 #pragma unroll
@@ -562,8 +578,7 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
     // the next tile's panel into the other buffer (its last readers finished
     // before the barrier that ended the previous tile)
     if (j + 1 < ntiles)
-      rr_stage<NT>(a.panel, a.gblk, kp, j + 1, lpb + ((j + 1) & 1) * NT * 1024,
-                   gtb + ((j + 1) & 1) * 2 * T * 16, tid);
+      rr_store<NT>(st, lpb + ((j + 1) & 1) * NT * 1024, gtb + ((j + 1) & 1) * 2 * T * 16, tid);
 #pragma unroll
     for (int jj = 0; jj < 4; jj++)
 #pragma unroll
