@@ -11,6 +11,7 @@ hals        FAST-HALS (Alg. 1) step by step, the tiled W/H update of Alg. 2
             (Eq. 4-6), the objective (Eq. 2) and the relative objective of
             Sec. 6.2, and H-only fold-in with W fixed.
 mlp         FP64 forward/backward/Adam for the fold-in warm-start network.
+mu          The multiplicative-update baseline (Sec. 2.1; Lee-Seung rules).
 tile_model  The data-movement model of Sec. 5 (Eq. 9-11), model only.
 """
-from . import hals, mlp, tile_model  # noqa: F401
+from . import hals, mlp, mu, tile_model  # noqa: F401

@@ -43,3 +43,34 @@ def test_planted_slip_is_caught(name, tmp_path):
                         "tests/test_oracle_hals.py"], cwd=tmp_path, capture_output=True, text=True,
                        timeout=300)
     assert r.returncode != 0, f"slip '{name}' passed every pin"
+
+
+MU_MUTATIONS = {
+    "MU H quotient inverted": ("return H * num / ((W.T @ W) @ H + delta)",
+                               "return H * ((W.T @ W) @ H + delta) / num"),
+    "MU W rule with the old factor dropped": ("return W * num / (W @ (H @ H.T) + delta)",
+                                              "return num / (W @ (H @ H.T) + delta)"),
+    "MU W rule with H^T H": ("W @ (H @ H.T) + delta", "W @ (H @ H.T) * 1.01 + delta"),
+    "MU W rule with the old H": ("    W = mu_w(A, W, H, delta)\n", "    W = mu_w(A, W, H0, delta)\n"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MU_MUTATIONS))
+def test_planted_mu_slip_is_caught(name, tmp_path):
+    src = open(os.path.join(ROOT, "oracle", "mu.py")).read()
+    a, b = MU_MUTATIONS[name]
+    assert a in src, "mutation anchor vanished: update the guard"
+    for d in ("oracle", "datagen"):
+        shutil.copytree(os.path.join(ROOT, d), tmp_path / d)
+    os.makedirs(tmp_path / "tests")
+    for f in ("conftest.py", "test_oracle_mu.py"):
+        shutil.copy(os.path.join(ROOT, "tests", f), tmp_path / "tests" / f)
+    mutated = src.replace(a, b, 1)
+    if "H0" in b:  # keep the sweep's original H in reach
+        mutated = mutated.replace("    H = mu_h(A, W, H, delta)\n", "    H0 = H\n    H = mu_h(A, W, H, delta)\n")
+    (tmp_path / "oracle" / "mu.py").write_text(mutated)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        "tests/test_oracle_mu.py"], cwd=tmp_path, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode != 0, f"slip '{name}' passed every pin"
