@@ -115,6 +115,16 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
  * plan.  A non-finite objective returns NMF_E_NUMERIC.                       */
 int nmf_sweep(nmf_plan plan, int n_sweeps, double* rel_obj);
 
+/* The multiplicative-update baseline (MU; Sec. 2.1 names it, after Lee and
+ * Seung, as the simplest NMF algorithm and the slower-converging comparator of
+ * Sec. 6.3): n_sweeps iterations of
+ *   H <- H * (W^T A) / (W^T W H + eps),   then   W <- W * (A H^T) / (W H H^T + eps)
+ * (elementwise; eps is the plan's) on the plan's W and Ht, with the same
+ * products, Grams, precision and objective as nmf_sweep and the same
+ * synchronisation and error behaviour.  W is not normalised (MU does not need
+ * it); a plan may mix nmf_sweep and nmf_mu_sweep.                            */
+int nmf_mu_sweep(nmf_plan plan, int n_sweeps, double* rel_obj);
+
 /* Run one half of a sweep: NMF_HALF_H forms R = A^T W and S = W^T W and updates
  * every row of H (Alg. 1, H loop); NMF_HALF_W forms P = A H^T and Q = H H^T and
  * updates every column of W with normalisation (Alg. 1, W loop).  Enqueue only:

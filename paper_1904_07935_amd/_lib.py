@@ -57,6 +57,7 @@ SIGNATURES = {
     "nmf_init": [POINTER(_P), POINTER(nmf_matrix), c_int, c_float, c_int, _P, _P, _P, c_size_t, _P],
     "nmf_sweep": [_P, c_int, POINTER(c_double)],
     "nmf_half": [_P, c_int],
+    "nmf_mu_sweep": [_P, c_int, POINTER(c_double)],
     "nmf_objective": [_P, POINTER(c_double), POINTER(c_double)],
     "nmf_intermediates": [_P, POINTER(_P), POINTER(_P), POINTER(_P), POINTER(_P)],
     "nmf_plan_info": [_P, POINTER(nmf_info)],

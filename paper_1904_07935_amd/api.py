@@ -109,6 +109,16 @@ class Plan:
         L.call("nmf_sweep", self.h, n, None)
         return None
 
+    def mu_sweep(self, n=1, objective=False):
+        """n iterations of the multiplicative-update baseline (nmf_mu_sweep)."""
+        self._sync_stream()
+        if objective:
+            out = (c_double * n)()
+            L.call("nmf_mu_sweep", self.h, n, out)
+            return list(out)
+        L.call("nmf_mu_sweep", self.h, n, None)
+        return None
+
     def half(self, which):
         self._sync_stream()
         L.call("nmf_half", self.h, {"H": L.NMF_HALF_H, "W": L.NMF_HALF_W}[which])

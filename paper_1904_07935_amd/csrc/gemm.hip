@@ -41,11 +41,11 @@ __device__ __forceinline__ float softplus_f(float z) {
 // here takes the address of the kernel argument block.
 __device__ __forceinline__ void epilogue(int epi, int64_t M, int64_t N, float* __restrict__ out,
                                          int64_t ldo, bool split, const float* __restrict__ bias,
-                                         const float* __restrict__ Dm, int64_t ldd,
-                                         void* __restrict__ C2, float* __restrict__ C,
+                                         const float* Dm, int64_t ldd,
+                                         void* __restrict__ C2, float* C,
                                          int64_t ldc, double* __restrict__ red_out,
                                          floatx16 (&acc)[2][2], int64_t r0, int64_t c0,
-                                         double* red_smem, bool mirror) {
+                                         double* red_smem, bool mirror, float mu_delta) {
   const int lane = threadIdx.x & 63;
   double ss = 0.0;
 #pragma unroll
@@ -79,6 +79,9 @@ __device__ __forceinline__ void epilogue(int epi, int64_t M, int64_t N, float* _
             const float d = v * gelu_grad_f(Dm[m * ldd + n]);
             if (C) C[m * ldc + n] = d;
             ((__bf16*)C2)[m * ldc + n] = (__bf16)d;
+          } else if (epi == EPI_MU) {
+            const float num = Dm[m * ldd + n], x = ((const float*)C2)[m * ldc + n];
+            C[m * ldc + n] = x * num / (v + mu_delta);
           }
         }
   if (epi == EPI_RESID_SQ) {
@@ -404,7 +407,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   float* out = split ? g.partial + (int64_t)blockIdx.z * M * N : g.C;
   epilogue(g.epi, M, N, out, split ? N : g.ldc, split, g.bias, g.D, g.ldd, g.C2, g.C, g.ldc,
            g.red_out, acc, m0 + wm * 64, n0 + wn * 64, red,
-           sym && !split && blockIdx.y != blockIdx.x);
+           sym && !split && blockIdx.y != blockIdx.x, g.mu_delta);
 }
 
 __global__ void splitk_reduce_kernel(const float* __restrict__ partial, int splits, int64_t M,

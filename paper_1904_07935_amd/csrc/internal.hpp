@@ -29,6 +29,8 @@ enum GemmEpi : int {
   EPI_BIAS_GELU = 2,  // C = acc + bias (pre-activation, FP32); C2 (bf16) = GELU(C)
   EPI_BIAS_SOFTPLUS = 3, // C = acc + bias (FP32); C2 (float) = softplus(C)
   EPI_GELU_GRAD = 4,  // C (FP32, if set) and C2 (bf16) = acc * GELU'(D), D = z1
+  EPI_MU = 5,         // C = D * X / (acc + mu_delta), X = (const float*)C2 (ld = ldc);
+                      // C may be D (each element is read, then written, by one thread)
 };
 
 struct GemmArgs {
@@ -48,6 +50,7 @@ struct GemmArgs {
   int64_t k_per_split;
   float* partial;  // [splits][M][N]
   int sym;         // 1: C is symmetric (M == N, op(A) = op(B)^T): upper tiles, mirrored
+  float mu_delta;  // EPI_MU: added to the denominator
 };
 
 enum class Elem { F32, BF16 };

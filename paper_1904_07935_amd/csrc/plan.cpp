@@ -398,6 +398,50 @@ int half_w(nmf_plan_s* p) {
   return NMF_OK;
 }
 
+// Multiplicative update (the MU baseline): X <- X * N / (X G + delta) with
+// N = R, G = S (H rule, X = Ht) or N = P, G = Q (W rule, X = W).  The
+// denominator is the matrix-core product X G, whose epilogue writes the new
+// values over N (each element read, then written, by one thread: X, the
+// product's operand, is left intact); they are then copied into X.
+hipError_t mu_update(nmf_plan_s* p, float* X, int64_t rows, float* N, const float* G) {
+  const int K = p->K;
+  GemmArgs g{};
+  g.A = X;
+  g.lda = K;
+  g.B = G;
+  g.ldb = K;
+  g.M = rows;
+  g.N = K;
+  g.Kd = K;
+  g.C = N;
+  g.ldc = K;
+  g.epi = EPI_MU;
+  g.D = N;
+  g.ldd = K;
+  g.C2 = X;
+  g.splits = 1;
+  g.mu_delta = p->eps;
+  hipError_t e = gemm(Elem::F32, false, false, g, p->stream);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(X, N, (size_t)rows * K * sizeof(float), hipMemcpyDeviceToDevice, p->stream);
+}
+
+int mu_half_h(nmf_plan_s* p) {
+  TIMED(p, NMF_STEP_GRAM_S, gram(p, p->W, p->V, p->S));
+  TIMED(p, NMF_STEP_PRODUCT_R, product_R(p));
+  TIMED(p, NMF_STEP_UPDATE_H, mu_update(p, p->Ht, p->D, p->R, p->S));
+  p->pq_valid = false;
+  return NMF_OK;
+}
+
+int mu_half_w(nmf_plan_s* p) {
+  TIMED(p, NMF_STEP_PRODUCT_P, product_P(p, false, p->P));
+  TIMED(p, NMF_STEP_GRAM_Q, gram(p, p->Ht, p->D, p->Q));
+  TIMED(p, NMF_STEP_UPDATE_W, mu_update(p, p->W, p->V, p->P, p->Q));
+  p->pq_valid = false;  // P now holds the new W
+  return NMF_OK;
+}
+
 int read_status(nmf_plan_s* p) {
   int32_t st = 0;
   HIPCHECK(p, hipMemcpyAsync(&st, p->status, sizeof(st), hipMemcpyDeviceToHost, p->stream));
@@ -641,6 +685,32 @@ int nmf_sweep(nmf_plan p, int n_sweeps, double* rel_obj) {
   // the device status word once per call (one 4-byte copy and one
   // synchronisation): a timed-out wait of the W update, here or in an earlier
   // nmf_half, poisons the plan now
+  int rc = read_status(p);
+  if (rc) return rc;
+  if (rel_obj) {
+    for (int i = 0; i < n_sweeps; i++)
+      if (!std::isfinite(rel_obj[i])) return fail(NMF_E_NUMERIC, "objective is not finite");
+  }
+  return NMF_OK;
+}
+
+int nmf_mu_sweep(nmf_plan p, int n_sweeps, double* rel_obj) {
+  if (!p) return fail(NMF_E_ARG, "plan is NULL");
+  if (p->poisoned) return fail(p->poisoned, "plan is poisoned by an earlier error");
+  if (n_sweeps < 0) return fail(NMF_E_ARG, "n_sweeps < 0");
+  for (int i = 0; i < n_sweeps; i++) {
+    int rc = mu_half_h(p);
+    if (rc) return rc;
+    rc = mu_half_w(p);
+    if (rc) return rc;
+    p->sweeps_done++;
+    if (rel_obj) {
+      rc = enqueue_objective(p);
+      if (rc) return rc;
+      HIPCHECK(p, hipMemcpyAsync(rel_obj + i, p->scal + 4, sizeof(double), hipMemcpyDeviceToHost,
+                                 p->stream));
+    }
+  }
   int rc = read_status(p);
   if (rc) return rc;
   if (rel_obj) {
