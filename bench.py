@@ -41,7 +41,7 @@ def parse(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c4"])
+    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--K", type=int, default=0, help="rank (default: the workload's own)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--profile-sweeps", type=int, default=5)
@@ -50,6 +50,11 @@ def parse(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tsync", action="store_true")
+    ap.add_argument("--tto", action="store_true",
+                    help="time-to-objective instead of throughput: FAST-HALS FP32 against "
+                         "its BF16-product form and the MU baseline (--config c1/c2/c4), "
+                         "or cold/WTA/network-warm fold-in (--config c3)")
+    ap.add_argument("--tto-sweeps", type=int, default=0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="afterwards, copy this many bytes device-to-device three times "
                          "(a kernel of known traffic for scaling HBM counters)")
@@ -270,6 +275,205 @@ def measure_t_sync(groups, K, dev):
                      f"column groups, per column"}
 
 
+# ------------------------------------------------------ time to objective ----
+
+TTO_SWEEPS = {"c1": 100, "c2": 100, "c4": 50}
+
+
+def _first(trace, pred):
+    for i, (t, f) in enumerate(trace):
+        if pred(i, f):
+            return i, t
+    return None, None
+
+
+def tto_full(args, dev):
+    """FAST-HALS FP32 (the reference), FAST-HALS with BF16 products and the MU
+    baseline from the same init: per sweep the event-timed sweep time
+    (objective off the clock) and the relative objective.  Target: the FP32
+    run's objective after the workload's sweep count plus 1e-4 (absolute, in
+    relative-objective units); also the alternative reading, the first sweep
+    whose relative decrease is below 1e-4."""
+    import numpy as np
+    import torch
+
+    from paper_1904_07935_amd.api import Matrix, Plan
+
+    n = args.tto_sweeps or TTO_SWEEPS[args.config]
+    A, W0, H0, cfg = load_workload(args.config, args.K, "fp32")
+    dense = cfg["format"] == "dense"
+    M = Matrix.from_dense(A, dev) if dense else Matrix.from_csr(A, dev)
+    runs = {}
+    for name, prec, algo in (("hals_fp32", "fp32", "hals"), ("hals_bf16", "bf16", "hals"),
+                             ("mu_fp32", "fp32", "mu")):
+        W = torch.tensor(W0, device=dev)
+        Ht = torch.tensor(np.ascontiguousarray(H0.T), device=dev)
+        plan = Plan(M, W, Ht, eps=1e-16, precision=prec)
+        step = plan.sweep if algo == "hals" else plan.mu_sweep
+        step(1)  # warm-up of the code paths, then back to the init
+        W.copy_(torch.tensor(W0, device=dev))
+        Ht.copy_(torch.tensor(np.ascontiguousarray(H0.T), device=dev))
+        plan.close()
+        plan = Plan(M, W, Ht, eps=1e-16, precision=prec)
+        step = plan.sweep if algo == "hals" else plan.mu_sweep
+        trace, tot = [], 0.0
+        for _ in range(n):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            step(1)
+            e1.record()
+            torch.cuda.synchronize()
+            tot += e0.elapsed_time(e1) / 1000.0
+            trace.append((tot, plan.objective()[1]))
+        plan.close()
+        del W, Ht
+        runs[name] = trace
+        print(f"[tto] {name}: {n} sweeps in {tot:.3f} s, final {trace[-1][1]:.6f}", file=sys.stderr,
+              flush=True)
+    f_ref = runs["hals_fp32"][-1][1]
+    target = f_ref + 1e-4
+    out = {"mode": "time_to_objective", "config": cfg, "sweeps": n, "f_ref": f_ref,
+           "target": target, "runs": {}}
+    for name, tr in runs.items():
+        i, t = _first(tr, lambda i, f: f <= target)
+        j, tj = _first(tr, lambda i, f: i > 0 and (tr[i - 1][1] - f) / tr[i - 1][1] < 1e-4)
+        out["runs"][name] = {"sweeps_to_target": None if i is None else i + 1,
+                             "seconds_to_target": t,
+                             "sweeps_to_rel_change_1e-4": None if j is None else j + 1,
+                             "seconds_to_rel_change_1e-4": tj,
+                             "final": tr[-1][1], "ms_per_sweep": 1000.0 * tr[-1][0] / n}
+    # time for each run to first reach a relative objective e, for a grid of e
+    # from the slowest run's final value up to the largest first-sweep value
+    hi = max(tr[0][1] for tr in runs.values())
+    lo = max(tr[-1][1] for tr in runs.values())
+    grid = [lo + (hi - lo) * x for x in (0.0, 0.01, 0.03, 0.1, 0.3, 0.6)]
+    out["time_to_reach"] = [
+        {"rel_objective": e, **{name: _first(tr, lambda i, f: f <= e)[1] for name, tr in runs.items()}}
+        for e in grid]
+    for name, tr in runs.items():
+        out["runs"][name]["trace"] = [round(f, 8) for _, f in tr]
+        out["runs"][name]["seconds"] = [round(t, 6) for t, _ in tr]
+    hb, hf = runs["hals_bf16"], runs["hals_fp32"]
+    out["bf16_vs_fp32_max_rel_diff"] = max(abs(b[1] - f[1]) / f[1] for b, f in zip(hb, hf))
+    # the MU run's final objective: when FAST-HALS FP32 first reached it
+    fm = runs["mu_fp32"][-1][1]
+    i, t = _first(hf, lambda i, f: f <= fm)
+    out["hals_time_to_mu_final"] = {"mu_final": fm, "hals_sweeps": None if i is None else i + 1,
+                                    "hals_seconds": t, "mu_seconds": runs["mu_fp32"][-1][0]}
+    print(json.dumps(out), flush=True)
+
+
+def _csr_rows(c, r0, r1):
+    import numpy as np
+
+    import datagen
+    a, b = int(c.rowptr[r0]), int(c.rowptr[r1])
+    return datagen.Csr(r1 - r0, c.cols, (c.rowptr[r0:r1 + 1] - a).astype(np.int32),
+                       c.col[a:b].copy(), c.val[a:b].copy())
+
+
+def tto_foldin(args, dev):
+    """Fold-in of new documents with W fixed: W from 100 FP32 sweeps of the
+    C1 corpus at K = 200; 200,000 new documents drawn like C1 (its term
+    permutation and idf, seed 3), the first 100,000 for training the network
+    on HALS-converged solutions, the rest for evaluation.  Target: the
+    cold-start fold-in's converged relative objective (decrease below 1e-9, at
+    most 500 sweeps) plus 1e-4.  Time to target for cold (U[0,1), seed 4),
+    WTA (max(eps, A^T W)) and network-warm starts, each a whole fold-in call
+    (product, Gram, initialisation -- the network's inference included -- and
+    the sweeps), event-timed."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_1904_07935_amd.api import Matrix, Mlp, Plan
+
+    K, hidden = 200, 512
+    corpus = datagen.c1()
+    V = corpus.A.rows
+    W0, H0 = datagen.uniform_init_matched(V, corpus.A.cols, K, datagen.mean_value(corpus.A), 1)
+    W = torch.tensor(W0, device=dev)
+    Ht = torch.tensor(np.ascontiguousarray(H0.T), device=dev)
+    plan = Plan(Matrix.from_csr(corpus.A, dev), W, Ht, eps=1e-16)
+    plan.sweep(100)
+    t0 = time.perf_counter()
+    docs = datagen.c3_docs(corpus, 200000, seed=3)
+    half = docs.rows // 2
+    train, evald = _csr_rows(docs, 0, half), _csr_rows(docs, half, docs.rows)
+    print(f"[tto] documents drawn in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    Mtr, Mev = Matrix.from_csr(train, dev), Matrix.from_csr(evald, dev)
+
+    def cold(c):
+        _, h = datagen.uniform_init_matched(V, c.rows, K, datagen.mean_value(c), seed=4)
+        return torch.tensor(np.ascontiguousarray(h.T), device=dev)
+
+    def timed_foldin(M, H, init, net, sweeps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        plan.foldin(M, H, init=init, mlp=net, n_sweeps=sweeps, trace=False)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1000.0
+
+    # training pairs: converged cold-start fold-in of the training documents
+    Hs = cold(train)
+    trs = plan.foldin(Mtr, Hs, init="given", n_sweeps=500, tol=1e-9)
+    R = torch.zeros(train.rows, K, device=dev)
+    plan.foldin(Mtr, R, init="wta", n_sweeps=0, trace=False)
+    nrm = R.norm(dim=1, keepdim=True).clamp_min(1e-30)
+    X, Y = (R / nrm).contiguous(), (Hs / nrm).contiguous()
+    net = Mlp(K, hidden, device=dev, seed=11)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    losses = net.train(X, Y, epochs=args.tto_sweeps or 200, batch=1024, lr=1e-3, seed=3)
+    e1.record()
+    torch.cuda.synchronize()
+    t_train = e0.elapsed_time(e1) / 1000.0
+    print(f"[tto] network trained in {t_train:.2f} s, loss {losses[0]:.3e} -> {losses[-1]:.3e}",
+          file=sys.stderr, flush=True)
+
+    ref = plan.foldin(Mev, cold(evald), init="given", n_sweeps=500, tol=1e-12)
+    target = ref[-1] + 1e-4
+    gaps = (1e-4, 1e-5, 1e-6, 1e-7, 1e-8)
+    out = {"mode": "time_to_objective", "config": {"workload": "c3_foldin_c1w_k200",
+           "V": V, "K": K, "train_docs": train.rows, "eval_docs": evald.rows,
+           "eval_nnz": int(evald.nnz), "hidden": hidden},
+           "f_ref": ref[-1], "ref_sweeps": len(ref) - 1, "target": target,
+           "train": {"pairs_sweeps": len(trs) - 1, "epochs": len(losses), "seconds": t_train,
+                     "loss_first": losses[0], "loss_last": losses[-1]},
+           "runs": {}}
+    for init in ("given", "wta", "mlp"):
+        H0e = cold(evald) if init == "given" else torch.zeros(evald.rows, K, device=dev)
+        tr = plan.foldin(Mev, H0e.clone(), init=init, mlp=net if init == "mlp" else None,
+                         n_sweeps=300)
+        hit = [i for i, f in enumerate(tr) if f <= target]
+        ns = hit[0] if hit else None
+        t_setup = timed_foldin(Mev, H0e.clone(), init, net if init == "mlp" else None, 0)
+        t_total = timed_foldin(Mev, H0e.clone(), init, net if init == "mlp" else None, ns) \
+            if ns is not None else None
+        name = {"given": "cold", "wta": "wta", "mlp": "mlp"}[init]
+        per_gap = {}
+        for g in gaps:
+            h = [i for i, f in enumerate(tr) if f <= ref[-1] + g]
+            per_gap[f"{g:g}"] = h[0] if h else None
+        t_sweep = (timed_foldin(Mev, H0e.clone(), init, net if init == "mlp" else None, 50)
+                   - t_setup) / 50.0
+        out["runs"][name] = {"rel_after_init": tr[0], "sweeps_to_target": ns,
+                             "seconds_to_target": t_total, "seconds_setup_and_init": t_setup,
+                             "seconds_per_sweep": t_sweep, "sweeps_to_within": per_gap,
+                             "trace_first_12": tr[:12]}
+        print(f"[tto] {name}: init {tr[0]:.6f}, sweeps to target {ns}", file=sys.stderr,
+              flush=True)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
 # ----------------------------------------------------------------- main ----
 
 def main():
@@ -290,6 +494,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.tto or args.config == "c3":
+        if args.config == "c3":
+            tto_foldin(args, dev)
+        else:
+            tto_full(args, dev)
+        return
     t_gen = time.perf_counter()
     A, W0, H0, cfg = load_workload(args.config, args.K, args.precision)
     t_gen = time.perf_counter() - t_gen

@@ -147,9 +147,24 @@ __device__ __forceinline__ V wave_elem(const V (&arr)[N], int k) {
   return __builtin_bit_cast(V, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k & 63));
 }
 
-template <int VPL, typename TV, typename TX, bool VEC>
+// Eight consecutive BF16 elements of a factor row (one 16-byte load) as floats.
+__device__ __forceinline__ void ld_x8(const __bf16* row, int c, int K, floatx4& lo, floatx4& hi) {
+  if (c < K) {
+    const bf16x8 b = *(const bf16x8*)(row + c);
+    lo = floatx4{(float)b[0], (float)b[1], (float)b[2], (float)b[3]};
+    hi = floatx4{(float)b[4], (float)b[5], (float)b[6], (float)b[7]};
+  } else {
+    lo = hi = floatx4{0, 0, 0, 0};
+  }
+}
+
+// EPL: factor elements per lane and load -- 4 (FP32 float4, or BF16 8-byte
+// loads), or 8 (BF16 16-byte loads; K % 8 == 0, rows 16-byte aligned).
+template <int VPL, typename TV, typename TX, bool VEC, int EPL = 4>
 __global__ __launch_bounds__(256) void spmm_flat(SpmmKArgs a) {
-  constexpr int UNR = VPL == 1 ? 16 : 8;
+  static_assert(EPL == 4 || (EPL == 8 && VEC && sizeof(TX) == 2), "16-byte BF16 loads only");
+  constexpr int NQ = EPL / 4;  // float4 accumulators per load
+  constexpr int UNR = VPL * NQ == 1 ? 16 : 8;
   constexpr int MZ = kFlatMaxNnz / 64;
   constexpr int MR = (kMaxRowsPerItem + 1 + 63) / 64;
   const int lane = threadIdx.x & 63;
@@ -179,37 +194,50 @@ __global__ __launch_bounds__(256) void spmm_flat(SpmmKArgs a) {
     const int e = wave_elem(prp, r + 1) - j0;
     return e < nz ? e : nz;
   };
-  floatx4 acc[VPL];
+  floatx4 acc[VPL * NQ];
 #pragma unroll
-  for (int v = 0; v < VPL; v++) acc[v] = floatx4{0, 0, 0, 0};
+  for (int v = 0; v < VPL * NQ; v++) acc[v] = floatx4{0, 0, 0, 0};
   int r = 0;
   int rend = nr > 0 ? row_end(0) : nz;
   auto flush = [&]() {
     float* dst = slot >= 0 ? a.carry + (int64_t)slot * K : a.out + (int64_t)(r0 + r) * K;
 #pragma unroll
     for (int v = 0; v < VPL; v++) {
-      const int cb = 4 * (lane + 64 * v);
-      if constexpr (VEC) {
-        if (cb < K) *(floatx4*)(dst + cb) = acc[v];
-      } else {
+      const int cb = EPL * (lane + 64 * v);
 #pragma unroll
-        for (int e = 0; e < 4; e++)
-          if (cb + e < K) dst[cb + e] = acc[v][e];
+      for (int q = 0; q < NQ; q++) {
+        if constexpr (VEC) {
+          if (cb < K) *(floatx4*)(dst + cb + 4 * q) = acc[v * NQ + q];
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; e++)
+            if (cb + e < K) dst[cb + e] = acc[v * NQ + q][e];
+        }
+        acc[v * NQ + q] = floatx4{0, 0, 0, 0};
       }
-      acc[v] = floatx4{0, 0, 0, 0};
     }
     r++;
     rend = r < nr ? row_end(r) : nz;
   };
   for (int jb = 0; jb < nz; jb += UNR) {
-    floatx4 x[UNR][VPL];
+    floatx4 x[UNR][VPL * NQ];
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
       const int j = jb + u;
       const int64_t col = j < nz ? wave_elem(pc, j) : 0;
 #pragma unroll
-      for (int v = 0; v < VPL; v++)
-        x[u][v] = j < nz ? ld_x4<TX, VEC>(X + col * K, 4 * (lane + 64 * v), K) : floatx4{0, 0, 0, 0};
+      for (int v = 0; v < VPL; v++) {
+        const int cb = EPL * (lane + 64 * v);
+        if constexpr (EPL == 8) {
+          if (j < nz) {
+            ld_x8((const __bf16*)(X + col * K), cb, K, x[u][v * NQ], x[u][v * NQ + 1]);
+          } else {
+            x[u][v * NQ] = x[u][v * NQ + 1] = floatx4{0, 0, 0, 0};
+          }
+        } else {
+          x[u][v] = j < nz ? ld_x4<TX, VEC>(X + col * K, cb, K) : floatx4{0, 0, 0, 0};
+        }
+      }
     }
 #pragma unroll
     for (int u = 0; u < UNR; u++) {
@@ -218,7 +246,7 @@ __global__ __launch_bounds__(256) void spmm_flat(SpmmKArgs a) {
         while (j >= rend && r < nr) flush();  // rows that end here, empty ones included
         const float vv = wave_elem(pv, j);
 #pragma unroll
-        for (int v = 0; v < VPL; v++) acc[v] += vv * x[u][v];
+        for (int v = 0; v < VPL * NQ; v++) acc[v] += vv * x[u][v];
       }
     }
   }
@@ -299,8 +327,17 @@ hipError_t launch_f(const SpmmKArgs& a, bool vec, hipStream_t s) {
 }
 
 template <typename TV, typename TX>
-hipError_t launch_k(const SpmmKArgs& a, bool vec, bool flat, hipStream_t s) {
+hipError_t launch_k(const SpmmKArgs& a, bool vec, bool vec8, bool flat, hipStream_t s) {
   const int n4 = (a.K + 3) / 4;
+  if constexpr (sizeof(TX) == 2) {
+    // BF16 rows longer than 256 elements: one 16-byte load of 8 per lane
+    if (flat && n4 > 64 && vec8) {
+      const unsigned blocks = (unsigned)((a.n_items + 3) / 4);
+      if (blocks == 0) return hipSuccess;
+      spmm_flat<1, TV, TX, true, 8><<<blocks, 256, 0, s>>>(a);
+      return hipGetLastError();
+    }
+  }
   if (flat && n4 > 32) return n4 <= 64 ? launch_f<1, TV, TX>(a, vec, s) : launch_f<2, TV, TX>(a, vec, s);
   if (n4 <= 1) return launch_t<1, 1, TV, TX>(a, vec, s);
   if (n4 <= 2) return launch_t<1, 2, TV, TX>(a, vec, s);
@@ -399,9 +436,10 @@ hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hip
   const size_t esz = t == Elem::F32 ? 4 : 2;
   const bool vec = (K % 4 == 0) && (((uintptr_t)X) % (4 * esz) == 0) &&
                    ((uintptr_t)out % 16 == 0) && ((uintptr_t)p.carry % 16 == 0);
+  const bool vec8 = vec && K % 8 == 0 && ((uintptr_t)X) % 16 == 0;
   const bool flat = p.L <= kFlatMaxNnz;  // the flat kernel holds a whole item in registers
-  hipError_t e = t == Elem::F32 ? launch_k<float, float>(a, vec, flat, s)
-                                : launch_k<__bf16, __bf16>(a, vec, flat, s);
+  hipError_t e = t == Elem::F32 ? launch_k<float, float>(a, vec, vec8, flat, s)
+                                : launch_k<__bf16, __bf16>(a, vec, vec8, flat, s);
   if (e != hipSuccess) return e;
   if (p.n_fix > 0) {
     spmm_fixup<<<(unsigned)p.n_fix, kFixThreads, 0, s>>>(p.fix, p.n_fix, p.carry, out, K);

@@ -53,10 +53,11 @@ def test_bf16_products_dense_error_stated(cuda):
     p16.close()
 
 
-@pytest.mark.parametrize("K", [24, 160])
+@pytest.mark.parametrize("K", [24, 160, 400])
 def test_bf16_products_sparse_error_stated(cuda, K):
     """K = 24: several nonzeros per wave step; K = 160: the one-nonzero-per-step
-    kernel with its prefetched item, gathering BF16 rows."""
+    kernel with its prefetched item, gathering BF16 rows; K = 400: the same with
+    one 16-byte load of eight BF16 values per lane."""
     c = small_bow()
     W0, H0 = sparse_init(c, K)
     rel_or, _ = oracle_run(c.A, W0, H0, 8)
@@ -72,6 +73,10 @@ def test_bf16_products_sparse_error_stated(cuda, K):
     Ao = oracle_A(c.A)
     R = np.asarray(Ao.T @ _np(p16.W))
     assert rel_fro(_np(mid["R"]), R) <= 1e-2
+    # exactly the product of the BF16-rounded inputs, up to FP32 accumulation
+    Ab = sp.csr_matrix((bf16_round(c.A.val), c.A.col, c.A.rowptr), shape=(c.A.rows, c.A.cols))
+    Rb = np.asarray(Ab.T @ bf16_round(_np(p16.W)))
+    assert elem_rel_max(_np(mid["R"]), Rb) <= 1e-4
     p16.close()
 
 
