@@ -236,6 +236,27 @@ def cpu_baseline(A, W0, H0, min_seconds, sample_div=0):
     return out
 
 
+def plnmf_cpu_baseline(A, W0, H0, min_seconds):
+    """PL-NMF-cpu (the paper's tiled Alg. 2 in FP64 with OpenMP, libplnmf_cpu.so)
+    on all host threads: one warm-up sweep, then whole sweeps for at least
+    min_seconds (at least one)."""
+    from paper_1904_07935_amd import cpu
+
+    p = cpu.CpuPlan(A, W0, H0)
+    p.sweep(1)
+    t0 = time.perf_counter()
+    done = 0
+    while done < 1 or (time.perf_counter() - t0 < min_seconds and done < 500):
+        p.sweep(1)
+        done += 1
+    dt = time.perf_counter() - t0
+    info = p.info()
+    p.close()
+    return {"value": done / dt, "unit": "sweeps/s", "cores": info["threads"], "tile": info["tile"],
+            "kind": "plnmf_cpu", "host_cpu": host_cpu(),
+            "sample": f"{done} full sweeps of the same workload after one warm-up, {dt:.1f} s"}
+
+
 # --------------------------------------------------------------- t_sync ----
 
 def measure_t_sync(groups, K, dev):
@@ -590,6 +611,7 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, W0, H0, args.cpu_seconds,
                                            sample_div=3 if args.config == "c4" else 0)
+        out["cpu_plnmf"] = plnmf_cpu_baseline(A, W0, H0, min(args.cpu_seconds, 5.0))
     print(json.dumps(out), flush=True)
 
 

@@ -47,6 +47,24 @@ def _compile(src):
     return obj, msgs
 
 
+CPU_SRC = os.path.join(HERE, "cpu", "plnmf_cpu.cpp")
+CPU_LIB = os.path.join(HERE, "libplnmf_cpu.so")
+
+
+def build_cpu(verbose=False):
+    """The PL-NMF-cpu baseline (FP64, OpenMP): a host library of its own."""
+    tmp = CPU_LIB + ".tmp"
+    cmd = [os.environ.get("CXX", "g++"), "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared",
+           "-std=c++17", "-Wall", CPU_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("g++ failed on plnmf_cpu.cpp:\n" + r.stdout + r.stderr)
+    if verbose and (r.stdout + r.stderr).strip():
+        print(r.stdout + r.stderr, file=sys.stderr)
+    shutil.move(tmp, CPU_LIB)
+    return CPU_LIB
+
+
 def build(verbose=False):
     os.makedirs(OUT_DIR, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
@@ -62,6 +80,7 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     shutil.move(tmp, LIB)
+    build_cpu(verbose)
     return LIB
 
 
