@@ -102,6 +102,10 @@ SpmmSizes spmm_sizes(int64_t rows, int64_t nnz, int L);
 // (synchronises the stream).  Device buffers must be sized by spmm_sizes.
 hipError_t spmm_build(SpmmPlan* p, hipStream_t s);
 hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hipStream_t s);
+// Columns [k0, k0 + K) only: out[r, k0 + c] = sum_j a[r, j] X[col_j, k0 + c],
+// X rows ldx apart, out rows ldo apart.
+hipError_t spmm_slice(const SpmmPlan& p, Elem t, const void* X, int64_t ldx, int k0, int K,
+                      float* out, int64_t ldo, hipStream_t s);
 
 // CSR transpose (rows x cols -> cols x rows), deterministic, rows sorted.
 // scratch: int32 [nblk * cols] (nblk from csr_transpose_blocks).

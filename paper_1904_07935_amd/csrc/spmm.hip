@@ -41,7 +41,8 @@ struct SpmmKArgs {
   float* out;
   float* carry;
   int64_t n_items;
-  int K;
+  int K;             // columns computed (a slice of the factor's columns, or all)
+  int64_t ldx, ldo;  // row strides of the factor and of the output
 };
 
 template <typename T>
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(256) void spmm_items(SpmmKArgs a) {
 #pragma unroll
       for (int u = 0; u < UNR; u++)
 #pragma unroll
-        for (int v = 0; v < VPL; v++) x[u][v] = ld_x4<TX, VEC>(X + (int64_t)cc[u] * K, 4 * (q + LPN * v), K);
+        for (int v = 0; v < VPL; v++) x[u][v] = ld_x4<TX, VEC>(X + (int64_t)cc[u] * a.ldx, 4 * (q + LPN * v), K);
 #pragma unroll
       for (int u = 0; u < UNR; u++)
 #pragma unroll
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(256) void spmm_items(SpmmKArgs a) {
       const int32_t cc = a.col[jj];
       const float vv = ld_val<TV>(a.val, jj);
 #pragma unroll
-      for (int v = 0; v < VPL; v++) acc[v] += vv * ld_x4<TX, VEC>(X + (int64_t)cc * K, 4 * (q + LPN * v), K);
+      for (int v = 0; v < VPL; v++) acc[v] += vv * ld_x4<TX, VEC>(X + (int64_t)cc * a.ldx, 4 * (q + LPN * v), K);
     }
     // combine the NPAR lane groups (fixed butterfly order)
 #pragma unroll
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) void spmm_items(SpmmKArgs a) {
       for (int v = 0; v < VPL; v++)
 #pragma unroll
         for (int e = 0; e < 4; e++) acc[v][e] += __shfl_xor(acc[v][e], off);
-    float* dst = slot >= 0 ? a.carry + (int64_t)slot * K : a.out + (int64_t)r * K;
+    float* dst = slot >= 0 ? a.carry + (int64_t)slot * K : a.out + (int64_t)r * a.ldo;
     if (grp == 0) {
 #pragma unroll
       for (int v = 0; v < VPL; v++) {
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(256) void spmm_flat(SpmmKArgs a) {
   int r = 0;
   int rend = nr > 0 ? row_end(0) : nz;
   auto flush = [&]() {
-    float* dst = slot >= 0 ? a.carry + (int64_t)slot * K : a.out + (int64_t)(r0 + r) * K;
+    float* dst = slot >= 0 ? a.carry + (int64_t)slot * K : a.out + (int64_t)(r0 + r) * a.ldo;
 #pragma unroll
     for (int v = 0; v < VPL; v++) {
       const int cb = EPL * (lane + 64 * v);
@@ -230,12 +231,12 @@ __global__ __launch_bounds__(256) void spmm_flat(SpmmKArgs a) {
         const int cb = EPL * (lane + 64 * v);
         if constexpr (EPL == 8) {
           if (j < nz) {
-            ld_x8((const __bf16*)(X + col * K), cb, K, x[u][v * NQ], x[u][v * NQ + 1]);
+            ld_x8((const __bf16*)(X + col * a.ldx), cb, K, x[u][v * NQ], x[u][v * NQ + 1]);
           } else {
             x[u][v * NQ] = x[u][v * NQ + 1] = floatx4{0, 0, 0, 0};
           }
         } else {
-          x[u][v] = j < nz ? ld_x4<TX, VEC>(X + col * K, cb, K) : floatx4{0, 0, 0, 0};
+          x[u][v] = j < nz ? ld_x4<TX, VEC>(X + col * a.ldx, cb, K) : floatx4{0, 0, 0, 0};
         }
       }
     }
@@ -262,7 +263,8 @@ constexpr int kFixThreads = 512;
 __global__ __launch_bounds__(kFixThreads) void spmm_fixup(const int32_t* __restrict__ fix,
                                                           int64_t n_fix,
                                                           const float* __restrict__ carry,
-                                                          float* __restrict__ out, int K) {
+                                                          float* __restrict__ out, int K,
+                                                          int64_t ldo) {
   __shared__ floatx4 part[kFixThreads];
   const int64_t i = blockIdx.x;
   if (i >= n_fix) return;
@@ -297,7 +299,7 @@ __global__ __launch_bounds__(kFixThreads) void spmm_fixup(const int32_t* __restr
   if (sl == 0 && t < nv) {
     floatx4 tot = part[v];
     for (int k = 1; k < S; k++) tot += part[k * nv + v];
-    float* dst = out + r * K + 4 * v;
+    float* dst = out + r * ldo + 4 * v;
     if (vec) {
       *(floatx4*)dst = tot;
     } else {
@@ -422,7 +424,17 @@ hipError_t spmm_build(SpmmPlan* p, hipStream_t s) {
 }
 
 hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hipStream_t s) {
+  return spmm_slice(p, t, X, K, 0, K, out, K, s);
+}
+
+hipError_t spmm_slice(const SpmmPlan& p, Elem t, const void* X0, int64_t ldx, int k0, int K,
+                      float* out0, int64_t ldo, hipStream_t s) {
+  const size_t esz = t == Elem::F32 ? 4 : 2;
+  const void* X = (const char*)X0 + (size_t)k0 * esz;
+  float* out = out0 + k0;
   SpmmKArgs a;
+  a.ldx = ldx;
+  a.ldo = ldo;
   a.rowptr = p.rowptr;
   a.col = p.col;
   a.val = p.val;
@@ -433,16 +445,16 @@ hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hip
   a.carry = p.carry;
   a.n_items = p.n_items;
   a.K = K;
-  const size_t esz = t == Elem::F32 ? 4 : 2;
-  const bool vec = (K % 4 == 0) && (((uintptr_t)X) % (4 * esz) == 0) &&
-                   ((uintptr_t)out % 16 == 0) && ((uintptr_t)p.carry % 16 == 0);
-  const bool vec8 = vec && K % 8 == 0 && ((uintptr_t)X) % 16 == 0;
+  const bool vec = (K % 4 == 0) && (ldx % 4 == 0) && (ldo % 4 == 0) &&
+                   (((uintptr_t)X) % (4 * esz) == 0) && ((uintptr_t)out % 16 == 0) &&
+                   ((uintptr_t)p.carry % 16 == 0);
+  const bool vec8 = vec && K % 8 == 0 && ldx % 8 == 0 && ((uintptr_t)X) % 16 == 0;
   const bool flat = p.L <= kFlatMaxNnz;  // the flat kernel holds a whole item in registers
   hipError_t e = t == Elem::F32 ? launch_k<float, float>(a, vec, vec8, flat, s)
                                 : launch_k<__bf16, __bf16>(a, vec, vec8, flat, s);
   if (e != hipSuccess) return e;
   if (p.n_fix > 0) {
-    spmm_fixup<<<(unsigned)p.n_fix, kFixThreads, 0, s>>>(p.fix, p.n_fix, p.carry, out, K);
+    spmm_fixup<<<(unsigned)p.n_fix, kFixThreads, 0, s>>>(p.fix, p.n_fix, p.carry, out, K, ldo);
     e = hipGetLastError();
   }
   return e;
