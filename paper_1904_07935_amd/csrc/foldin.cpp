@@ -58,7 +58,8 @@ FoldWs fold_layout(void* base, int64_t Dn, int64_t V, int K, const nmf_matrix* A
   }
   f.partial = c.take<float>(part);
   f.gpart = c.take<float>(gram_partial_floats(K, gram_max_chunks()));
-  f.panel = c.take<float>(hals_panel_floats(K));
+  f.panel = c.take<float>(std::max(std::max(hals_panel_floats(K, 16), hals_panel_floats(K, 32)),
+                                    hals_panel_floats(K, 64)));
   f.red = c.take<double>(1024);
   f.scal = c.take<double>(8);
   f.trace = c.take<double>(kTraceChunk);
@@ -84,8 +85,8 @@ FoldWs fold_layout(void* base, int64_t Dn, int64_t V, int K, const nmf_matrix* A
 }
 
 hipError_t gram_with(const float* X, int64_t rows, int K, float* out, float* gpart, int cus,
-                     hipStream_t s, float* panel = nullptr) {
-  return gram_xtx(X, rows, K, out, K, gpart, gram_chunks(rows, cus), s, panel, 1);
+                     hipStream_t s, float* panel = nullptr, int tile = 32) {
+  return gram_xtx(X, rows, K, out, K, gpart, gram_chunks(rows, cus), s, panel, 1, tile);
 }
 
 #define FCHECK(expr)                                                                      \
@@ -213,8 +214,10 @@ int plnmf::foldin_run(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int in
     FCHECK(sumsq_f64(AnewT->dense, Dn * p->V, f.red, nb, s));
     FCHECK(finish_f64(f.red, nb, f.scal + 0, s));
   }
-  FCHECK(hipMemsetAsync(f.panel, 0, hals_panel_floats(K) * sizeof(float), s));
-  FCHECK(gram_with(p->W, p->V, K, f.S, f.gpart, p->cus, s, f.panel));
+  FCHECK(hipMemsetAsync(f.panel, 0,
+                        std::max(std::max(hals_panel_floats(K, 16), hals_panel_floats(K, 32)),
+                                 hals_panel_floats(K, 64)) * sizeof(float), s));
+  FCHECK(gram_with(p->W, p->V, K, f.S, f.gpart, p->cus, s, f.panel, p->h_tile));
 
   // initialisation of H for the new documents
   if (init_mode == NMF_FOLDIN_WTA) {
@@ -235,6 +238,7 @@ int plnmf::foldin_run(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int in
   a.eps = p->eps;
   a.diag_one = 1;
   a.panel = f.panel;
+  a.tile = p->h_tile;
   int filled = 0;  // trace entries waiting in f.trace
   int written = 0; // trace entries copied to the host
   auto flush = [&]() -> int {

@@ -144,20 +144,22 @@ constexpr int kRedThreads = 32 * kRedSlices;
 // operand of the tile of col, contraction row l): 1 - C or 0 on the diagonal,
 // 0 for l inside the tile and left of col, -C elsewhere.  Same layout as the
 // update kernels read: panel[j][l][c] (l < kpad(K), c < 32), then gblk[j][t][c].
-__device__ __forceinline__ void put_panel(float* panel, int K, int diag_one, int l, int col, float v) {
-  const int kp = (K + 7) / 8 * 8, ntiles = (K + 31) / 32;
-  const int j = col / 32, c = col % 32, a0 = 32 * j;
+__device__ __forceinline__ void put_panel(float* panel, int K, int diag_one, int tile, int l, int col,
+                                          float v) {
+  const int kp = (K + 7) / 8 * 8, ntiles = (K + tile - 1) / tile;
+  const int j = col / tile, c = col % tile, a0 = tile * j;
   float pv;
   if (l == col) pv = diag_one ? 1.0f - v : 0.0f;
   else if (l >= a0 && l < col) pv = 0.0f;
   else pv = -v;
-  panel[((int64_t)j * kp + l) * 32 + c] = pv;
-  if (l / 32 == j) panel[(int64_t)ntiles * kp * 32 + ((int64_t)j * 32 + (l - a0)) * 32 + c] = v;
+  panel[((int64_t)j * kp + l) * tile + c] = pv;
+  if (l / tile == j)
+    panel[(int64_t)ntiles * kp * tile + ((int64_t)j * tile + (l - a0)) * tile + c] = v;
 }
 
 __global__ __launch_bounds__(kRedThreads) void gram_reduce(const float* __restrict__ partial, int nchunks,
                                                     int K, float* __restrict__ C, int64_t ldc,
-                                                    float* __restrict__ panel, int diag_one) {
+                                                    float* __restrict__ panel, int diag_one, int tile) {
   __shared__ floatx4 part[kRedThreads];
   const int nb = nblk(K), nu = upper_blocks(K);
   const int u = blockIdx.x / 8, piece = blockIdx.x % 8;
@@ -200,8 +202,8 @@ __global__ __launch_bounds__(kRedThreads) void gram_reduce(const float* __restri
         C[(int64_t)gi * ldc + gj] = tot[e];
         if (bi != bj) C[(int64_t)gj * ldc + gi] = tot[e];
         if (panel) {
-          put_panel(panel, K, diag_one, gi, gj, tot[e]);
-          if (bi != bj) put_panel(panel, K, diag_one, gj, gi, tot[e]);
+          put_panel(panel, K, diag_one, tile, gi, gj, tot[e]);
+          if (bi != bj) put_panel(panel, K, diag_one, tile, gj, gi, tot[e]);
         }
       }
     }
@@ -224,7 +226,7 @@ int gram_chunks(int64_t rows, int device_cus) {
 size_t gram_partial_floats(int K, int chunks) { return (size_t)chunks * upper_blocks(K) * 1024; }
 
 hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, float* partial,
-                    int chunks, hipStream_t s, float* panel, int diag_one) {
+                    int chunks, hipStream_t s, float* panel, int diag_one, int tile) {
   if (K <= 0) return hipSuccess;
   if (K > kMaxK || chunks < 1) return hipErrorInvalidValue;
   const int64_t rpc = (rows + chunks - 1) / chunks;
@@ -242,7 +244,7 @@ hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   gram_reduce<<<(unsigned)(upper_blocks(K) * 8), kRedThreads, 0, s>>>(partial, chunks, K, C, ldc, panel,
-                                                                diag_one);
+                                                                diag_one, tile);
   return hipGetLastError();
 }
 

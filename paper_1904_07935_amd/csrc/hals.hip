@@ -444,78 +444,103 @@ hipError_t allow_smem(const void* fn, size_t bytes) {
 // them.  Compared with the LDS-resident kernel, which holds 32 rows and a
 // panel per workgroup, four times as many rows share one panel and every
 // SIMD runs its own wave's product and phase 2.
-// LDS (floats): panel [2][32 NT][32] | gh [2][2][T][16] | part [4][32][TP].
+//
+// The tile width TT (the paper's T) is a template parameter: 32 is the
+// product's output width; 64 takes two 32-column products per tile; 16 uses
+// half of each 32-column product (the other half multiplies zeros).
+// LDS (floats): panel [2][NB][32 NT][32] | gh [2][TT][TT] | part [4][32][TT + 1],
+// NB = max(1, TT / 32).
 constexpr int kRowsRR = 32;    // rows per wave
 constexpr int kWavesRR = 4;    // waves per workgroup
-__host__ __device__ inline size_t rr_smem_floats(int NT) {
-  return 2 * (size_t)NT * 1024 + 2 * 2 * T * 16 + kWavesRR * 32 * TP;
+__host__ __device__ constexpr int rr_nb(int TT) { return TT >= 32 ? TT / 32 : 1; }
+__host__ __device__ constexpr int rr_pp(int TT) { return TT + 1 > TP ? TT + 1 : TP; }  // part pitch
+__host__ __device__ inline size_t rr_smem_floats(int NT, int TT) {
+  return 2 * (size_t)rr_nb(TT) * NT * 1024 + 2 * (size_t)TT * TT + kWavesRR * 32 * rr_pp(TT);
 }
+constexpr size_t kRrLdsMax = 160 * 1024;
 
-// Stage tile j's panel (kpad(K) rows of 32, then zeros up to 32 NT rows) and
-// its G block: all threads; the panel in lane-read order
-// ((t * 4 + q) * 2 + h) * 32 + m float4s, holding rows 32 t + 2 (4 q + i) + h;
-// the G block split by column parity, gh[h][t][k] = G[t][2 k + h] for
-// 2 k + h > t and 0 otherwise (the columns a step updates).
-template <int NT>
+// Tile j's staging: the panel (kpad(K) rows of TT, zeros up to 32 NT rows) in
+// lane-read order -- float4 (((q NT + t) 4 + sq) 2 + h) 32 + m holds rows
+// 32 t + 2 (4 sq + i) + h of column 32 q + m -- and the G block split by
+// column parity, gh[h][t][k] = G[t][2 k + h] for 2 k + h > t, else 0 (the
+// columns a phase-2 step updates).  Loads are issued by rr_load (early),
+// stores by rr_store.
+template <int NT, int TT>
 struct RrStage {
-  floatx4 v[NT];  // thread tid's float4s tid + 256 k of the panel
-  floatx4 g;      // its four G-block entries
+  static constexpr int NP = (NT * 32 * (TT / 4) + 255) / 256;
+  static constexpr int NG = (TT * TT + 255) / 256;
+  floatx4 v[NP];
+  float g[NG];
 };
 
-// Global loads of tile j's staging (issued early, stored by rr_store).
-template <int NT>
+template <int NT, int TT>
 __device__ __forceinline__ void rr_load(const float* __restrict__ panel, const float* __restrict__ gblk,
-                                        int kp, int j, int tid, RrStage<NT>& st) {
-  const floatx4* src = (const floatx4*)(panel + (int64_t)j * kp * T);
+                                        int kp, int j, int tid, RrStage<NT, TT>& st) {
+  constexpr int Q4 = TT / 4, N4 = NT * 32 * Q4, NP = RrStage<NT, TT>::NP;
+  const floatx4* src = (const floatx4*)(panel + (int64_t)j * kp * TT);
 #pragma unroll
-  for (int k = 0; k < NT; k++) {
-    const int i = tid + 256 * k, l = i >> 3;
-    st.v[k] = l < kp ? src[i] : floatx4{0, 0, 0, 0};
+  for (int k = 0; k < NP; k++) {
+    const int i = tid + 256 * k, l = i / Q4;
+    st.v[k] = (i < N4 && l < kp) ? src[i] : floatx4{0, 0, 0, 0};
   }
-  const float* gs = gblk + (int64_t)j * T * T;
-  const int idx = 4 * tid, h = idx >> 9, t = (idx >> 4) & 31, k0 = idx & 15;
+  const float* gs = gblk + (int64_t)j * TT * TT;
 #pragma unroll
-  for (int e = 0; e < 4; e++) {
-    const int c = 2 * (k0 + e) + h;
-    st.g[e] = c > t ? gs[t * T + c] : 0.0f;
+  for (int k = 0; k < RrStage<NT, TT>::NG; k++) {
+    const int idx = tid + 256 * k, h = idx / (TT * TT / 2), t = (idx / (TT / 2)) % TT,
+              kk = idx % (TT / 2), c = 2 * kk + h;
+    st.g[k] = (idx < TT * TT && c > t) ? gs[t * TT + c] : 0.0f;
   }
 }
 
-template <int NT>
-__device__ __forceinline__ void rr_store(const RrStage<NT>& st, float* lp, float* gt, int tid) {
+template <int NT, int TT>
+__device__ __forceinline__ void rr_store(const RrStage<NT, TT>& st, float* lp, float* gt, int tid) {
+  constexpr int Q4 = TT / 4, N4 = NT * 32 * Q4, NP = RrStage<NT, TT>::NP;
 #pragma unroll
-  for (int k = 0; k < NT; k++) {
+  for (int k = 0; k < NP; k++) {
     const int i = tid + 256 * k;
-    const int l = i >> 3, c0 = 4 * (i & 7);
-    const int t = l >> 5, r = l & 31, s2 = r >> 1, h = r & 1, q = s2 >> 2, ii = s2 & 3;
-    float* d = lp + ((((t * 4 + q) * 2 + h) * 32 + c0) * 4) + ii;
-    d[0] = st.v[k][0];
-    d[4] = st.v[k][1];
-    d[8] = st.v[k][2];
-    d[12] = st.v[k][3];
+    if (i < N4) {
+      const int l = i / Q4, c0 = 4 * (i % Q4), q = c0 >> 5, m0 = c0 & 31;
+      const int t = l >> 5, r = l & 31, s2 = r >> 1, h = r & 1, sq = s2 >> 2, ii = s2 & 3;
+      float* d = lp + (((((q * NT + t) * 4 + sq) * 2 + h) * 32 + m0) * 4) + ii;
+      d[0] = st.v[k][0];
+      d[4] = st.v[k][1];
+      d[8] = st.v[k][2];
+      d[12] = st.v[k][3];
+    }
   }
-  *(floatx4*)(gt + 4 * tid) = st.g;
+#pragma unroll
+  for (int k = 0; k < RrStage<NT, TT>::NG; k++) {
+    const int idx = tid + 256 * k;
+    if (idx < TT * TT) gt[idx] = st.g[k];
+  }
 }
 
-template <int NT, bool VEC>
+template <int NT, int TT, bool VEC>
 __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
+  constexpr int NB = rr_nb(TT), HP = TT / 2, PP = rr_pp(TT);
   extern __shared__ float smem_raw[];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 31, h = lane >> 5;
-  const int K = a.K, kp = kpad(K), ntiles = (K + T - 1) / T;
-  float* lpb = smem_raw;                 // [2][NT * 1024]
-  float* gtb = lpb + 2 * NT * 1024;      // [2][2 * T * 16]
-  float* part = gtb + 2 * 2 * T * 16 + w * 32 * TP;
+  const int K = a.K, kp = kpad(K), ntiles = (K + TT - 1) / TT;
+  float* lpb = smem_raw;                           // [2][NB * NT * 1024]
+  float* gtb = lpb + 2 * NB * NT * 1024;           // [2][TT * TT]
+  float* part = gtb + 2 * TT * TT + w * 32 * PP;   // this wave's [32][TT + 1]
   const int64_t row0 = ((int64_t)blockIdx.x * kWavesRR + w) * kRowsRR;
   const int nr = a.rows - row0 < kRowsRR ? (int)(a.rows - row0) : kRowsRR;  // may be <= 0
   const float eps = a.eps;
   float* __restrict__ X = a.X;
 
-  {
-    RrStage<NT> st;
-    rr_load<NT>(a.panel, a.gblk, kp, 0, tid, st);
-    rr_store<NT>(st, lpb, gtb, tid);
+  if constexpr (TT < 32) {
+    // the panel columns a 16-wide tile leaves unused stay zero
+    for (int i = tid; i < 2 * NB * NT * 1024; i += 256) lpb[i] = 0.0f;
+    __syncthreads();
   }
-  // the wave's rows into the A-operand layout, one 32-column tile at a time
+  {
+    RrStage<NT, TT> st;
+    rr_load<NT, TT>(a.panel, a.gblk, kp, 0, tid, st);
+    rr_store<NT, TT>(st, lpb, gtb, tid);
+  }
+  // the wave's rows into the A-operand layout, 32 columns at a time (the
+  // transpose goes through the first 32 x 33 floats of part)
   float xa[16 * NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) {
@@ -546,66 +571,75 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
 
 #pragma unroll 1
   for (int j = 0; j < ntiles; j++) {
-    const int a0 = j * T, tw = a0 + T < K ? T : K - a0;
-    const float* lp = lpb + (j & 1) * NT * 1024;
-    const float* gt = gtb + (j & 1) * 2 * T * 16;
+    const int a0 = j * TT, tw = a0 + TT < K ? TT : K - a0;
+    const float* lp = lpb + (j & 1) * NB * NT * 1024;
+    const float* gt = gtb + (j & 1) * TT * TT;
     // Bterm of the tile in the product's lane layout
-    float bt[16];
+    float bt[NB][16];
 #pragma unroll
-    for (int jj = 0; jj < 4; jj++)
+    for (int q = 0; q < NB; q++)
 #pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int rl = 8 * jj + 4 * h + i;
-        bt[4 * jj + i] = (rl < nr && m < tw) ? a.Bterm[(row0 + rl) * K + a0 + m] : 0.0f;
-      }
+      for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int rl = 8 * jj + 4 * h + i, c = 32 * q + m;
+          bt[q][4 * jj + i] = (rl < nr && c < tw) ? a.Bterm[(row0 + rl) * K + a0 + c] : 0.0f;
+        }
     // the next tile's staging: global loads now, LDS stores after the product
-    RrStage<NT> st;
-    if (j + 1 < ntiles) rr_load<NT>(a.panel, a.gblk, kp, j + 1, tid, st);
+    RrStage<NT, TT> st;
+    if (j + 1 < ntiles) rr_load<NT, TT>(a.panel, a.gblk, kp, j + 1, tid, st);
     // the tile product over the whole contraction, B operand from LDS
-    floatx16 acc;
+    floatx16 acc[NB];
 #pragma unroll
-    for (int e = 0; e < 16; e++) acc[e] = 0.0f;
+    for (int q = 0; q < NB; q++)
+#pragma unroll
+      for (int e = 0; e < 16; e++) acc[q][e] = 0.0f;
 #pragma unroll
     for (int t = 0; t < NT; t++) {
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const floatx4 b = *(const floatx4*)(lp + (((t * 4 + q) * 2 + h) * 32 + m) * 4);
+      for (int sq = 0; sq < 4; sq++) {
 #pragma unroll
-        for (int i = 0; i < 4; i++)
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[16 * t + 4 * q + i], b[i], acc, 0, 0, 0);
+        for (int q = 0; q < NB; q++) {
+          const floatx4 b = *(const floatx4*)(lp + ((((q * NT + t) * 4 + sq) * 2 + h) * 32 + m) * 4);
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[16 * t + 4 * sq + i], b[i], acc[q], 0, 0, 0);
+        }
       }
     }
-    // the next tile's panel into the other buffer (its last readers finished
-    // before the barrier that ended the previous tile)
     if (j + 1 < ntiles)
-      rr_store<NT>(st, lpb + ((j + 1) & 1) * NT * 1024, gtb + ((j + 1) & 1) * 2 * T * 16, tid);
+      rr_store<NT, TT>(st, lpb + ((j + 1) & 1) * NB * NT * 1024, gtb + ((j + 1) & 1) * TT * TT, tid);
 #pragma unroll
-    for (int jj = 0; jj < 4; jj++)
+    for (int q = 0; q < NB; q++)
 #pragma unroll
-      for (int i = 0; i < 4; i++) part[(8 * jj + 4 * h + i) * TP + m] = acc[4 * jj + i] + bt[4 * jj + i];
+      for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          if (32 * q + m < TT)
+            part[(8 * jj + 4 * h + i) * PP + 32 * q + m] = acc[q][4 * jj + i] + bt[q][4 * jj + i];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // phase 2 on all lanes: lane (m, h) holds row m's columns 2 k + h
-    float yh[16];
+    float yh[HP];
 #pragma unroll
-    for (int k = 0; k < 16; k++) yh[k] = part[m * TP + 2 * k + h];
+    for (int k = 0; k < HP; k++) yh[k] = part[m * PP + 2 * k + h];
     {
-      const float* gp = gt + h * T * 16;
-      float gc[16], gn[16];
+      const float* gp = gt + h * TT * HP;
+      float gc[HP], gn[HP];
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
+      for (int q = 0; q < HP / 4; q++) {
         const floatx4 v = *(const floatx4*)(gp + 4 * q);
 #pragma unroll
         for (int e = 0; e < 4; e++) gc[4 * q + e] = v[e];
       }
 #pragma unroll
-      for (int t = 0; t < T; t++) {
+      for (int t = 0; t < TT; t++) {
         const int u = t >> 1;
-        if (t + 1 < T) {  // step t + 1's G row, loaded during step t
+        if (t + 1 < TT) {  // step t + 1's G row, loaded during step t
 #pragma unroll
-          for (int q = ((t + 1) >> 1) >> 2; q < 4; q++) {
-            const floatx4 v = *(const floatx4*)(gp + (t + 1) * 16 + 4 * q);
+          for (int q = ((t + 1) >> 1) >> 2; q < HP / 4; q++) {
+            const floatx4 v = *(const floatx4*)(gp + (t + 1) * HP + 4 * q);
 #pragma unroll
             for (int e = 0; e < 4; e++) gn[4 * q + e] = v[e];
           }
@@ -619,43 +653,56 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
         const float x = __uint_as_float((t & 1) ? sw[1] : sw[0]);
         yh[u] = h == (t & 1) ? x : yh[u];
 #pragma unroll
-        for (int k = u; k < 16; k++) yh[k] -= x * gc[k];  // gc is 0 for columns <= t
+        for (int k = u; k < HP; k++) yh[k] -= x * gc[k];  // gc is 0 for columns <= t
 #pragma unroll
-        for (int k = (t + 1) >> 1; k < 16; k++) gc[k] = gn[k];
+        for (int k = (t + 1) >> 1; k < HP; k++) gc[k] = gn[k];
       }
     }
-    if (tw < T) {
+    if (tw < TT) {
 #pragma unroll
-      for (int k = 0; k < 16; k++)
+      for (int k = 0; k < HP; k++)
         if (2 * k + h >= tw) yh[k] = 0.0f;
     }
     // the new tile values: into xa, and through part to the rows in global memory
 #pragma unroll
-    for (int t = 0; t < NT; t++)
-      if (t == j) {  // uniform: one branch per tile, no copy of xa
+    for (int t = 0; t < NT; t++) {
+      if constexpr (TT >= 32) {
 #pragma unroll
-        for (int k = 0; k < 16; k++) xa[16 * t + k] = yh[k];
+        for (int q = 0; q < NB; q++)
+          if (t == NB * j + q) {  // uniform: one branch per 32 columns, no copy of xa
+#pragma unroll
+            for (int s2 = 0; s2 < 16; s2++) xa[16 * t + s2] = yh[16 * q + s2];
+          }
+      } else {
+        if (2 * t == j) {
+#pragma unroll
+          for (int s2 = 0; s2 < 8; s2++) xa[16 * t + s2] = yh[s2];
+        } else if (2 * t + 1 == j) {
+#pragma unroll
+          for (int s2 = 0; s2 < 8; s2++) xa[16 * t + 8 + s2] = yh[s2];
+        }
       }
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-    for (int k = 0; k < 16; k++) part[m * TP + 2 * k + h] = yh[k];
+    for (int k = 0; k < HP; k++) part[m * PP + 2 * k + h] = yh[k];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     {
-      const int rl = lane >> 1, c0 = 16 * (lane & 1);  // row rl, columns c0 .. c0 + 15
+      const int rl = lane >> 1, c0 = HP * (lane & 1);  // row rl, columns c0 .. c0 + HP - 1
       if (rl < nr) {
         float* dst = X + (row0 + rl) * K + a0 + c0;
-        const float* sp = part + rl * TP + c0;
-        if (VEC && tw == T) {
+        const float* sp = part + rl * PP + c0;
+        if (VEC && tw == TT) {
 #pragma unroll
-          for (int q = 0; q < 4; q++)
+          for (int q = 0; q < HP / 4; q++)
             *(floatx4*)(dst + 4 * q) = floatx4{sp[4 * q], sp[4 * q + 1], sp[4 * q + 2], sp[4 * q + 3]};
         } else {
 #pragma unroll
-          for (int c = 0; c < 16; c++)
+          for (int c = 0; c < HP; c++)
             if (c0 + c < tw) dst[c] = sp[c];
         }
       }
@@ -665,38 +712,57 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
   }
 }
 
-template <int NT>
+template <int NT, int TT>
 hipError_t launch_h_rows(const HalsArgs& b, bool vec, hipStream_t s) {
   const unsigned grid = (unsigned)((b.rows + kWavesRR * kRowsRR - 1) / (kWavesRR * kRowsRR));
-  const size_t bytes = rr_smem_floats(NT) * 4;
-  const void* fn = vec ? (const void*)hals_h_rows_kernel<NT, true> : (const void*)hals_h_rows_kernel<NT, false>;
-  hipError_t e = allow_smem(fn, bytes);
-  if (e != hipSuccess) return e;
-  if (vec) hals_h_rows_kernel<NT, true><<<grid, 256, bytes, s>>>(b);
-  else hals_h_rows_kernel<NT, false><<<grid, 256, bytes, s>>>(b);
+  const size_t bytes = rr_smem_floats(NT, TT) * 4;
+  if (bytes > kRrLdsMax) return hipErrorInvalidValue;
+  if constexpr (TT == 64 && NT > 6) {
+    return hipErrorInvalidValue;  // the double-buffered 64-wide panel exceeds the LDS
+  } else if constexpr (TT == 32) {
+    const void* fn = vec ? (const void*)hals_h_rows_kernel<NT, TT, true>
+                         : (const void*)hals_h_rows_kernel<NT, TT, false>;
+    hipError_t e = allow_smem(fn, bytes);
+    if (e != hipSuccess) return e;
+    if (vec) hals_h_rows_kernel<NT, TT, true><<<grid, 256, bytes, s>>>(b);
+    else hals_h_rows_kernel<NT, TT, false><<<grid, 256, bytes, s>>>(b);
+  } else {
+    if (!vec) return hipErrorInvalidValue;  // other widths: K % 4 == 0 only
+    const void* fn = (const void*)hals_h_rows_kernel<NT, TT, true>;
+    hipError_t e = allow_smem(fn, bytes);
+    if (e != hipSuccess) return e;
+    hals_h_rows_kernel<NT, TT, true><<<grid, 256, bytes, s>>>(b);
+  }
   return hipGetLastError();
 }
 
-hipError_t h_rows_dispatch(const HalsArgs& b, bool vec, hipStream_t s) {
-  switch ((b.K + T - 1) / T) {
-    case 1: return launch_h_rows<1>(b, vec, s);
-    case 2: return launch_h_rows<2>(b, vec, s);
-    case 3: return launch_h_rows<3>(b, vec, s);
-    case 4: return launch_h_rows<4>(b, vec, s);
-    case 5: return launch_h_rows<5>(b, vec, s);
-    case 6: return launch_h_rows<6>(b, vec, s);
-    case 7: return launch_h_rows<7>(b, vec, s);
-    case 8: return launch_h_rows<8>(b, vec, s);
-    case 9: return launch_h_rows<9>(b, vec, s);
-    case 10: return launch_h_rows<10>(b, vec, s);
-    case 11: return launch_h_rows<11>(b, vec, s);
-    case 12: return launch_h_rows<12>(b, vec, s);
-    case 13: return launch_h_rows<13>(b, vec, s);
-    case 14: return launch_h_rows<14>(b, vec, s);
-    case 15: return launch_h_rows<15>(b, vec, s);
-    case 16: return launch_h_rows<16>(b, vec, s);
+template <int TT>
+hipError_t h_rows_tt(const HalsArgs& b, bool vec, hipStream_t s) {
+  switch ((b.K + 31) / 32) {
+    case 1: return launch_h_rows<1, TT>(b, vec, s);
+    case 2: return launch_h_rows<2, TT>(b, vec, s);
+    case 3: return launch_h_rows<3, TT>(b, vec, s);
+    case 4: return launch_h_rows<4, TT>(b, vec, s);
+    case 5: return launch_h_rows<5, TT>(b, vec, s);
+    case 6: return launch_h_rows<6, TT>(b, vec, s);
+    case 7: return launch_h_rows<7, TT>(b, vec, s);
+    case 8: return launch_h_rows<8, TT>(b, vec, s);
+    case 9: return launch_h_rows<9, TT>(b, vec, s);
+    case 10: return launch_h_rows<10, TT>(b, vec, s);
+    case 11: return launch_h_rows<11, TT>(b, vec, s);
+    case 12: return launch_h_rows<12, TT>(b, vec, s);
+    case 13: return launch_h_rows<13, TT>(b, vec, s);
+    case 14: return launch_h_rows<14, TT>(b, vec, s);
+    case 15: return launch_h_rows<15, TT>(b, vec, s);
+    case 16: return launch_h_rows<16, TT>(b, vec, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t h_rows_dispatch(const HalsArgs& b, bool vec, hipStream_t s) {
+  if (b.tile == 16) return h_rows_tt<16>(b, vec, s);
+  if (b.tile == 64) return h_rows_tt<64>(b, vec, s);
+  return h_rows_tt<32>(b, vec, s);
 }
 
 // ---------------------------------------------------------------- W half ----
@@ -1246,9 +1312,16 @@ static bool h_rows_kernel_for(int64_t rows, int K) {
   return rows >= 32768;
 }
 
-size_t hals_panel_floats(int K) {
-  const int ntiles = (K + T - 1) / T;
-  return (size_t)ntiles * kpad(K) * T + (size_t)ntiles * T * T;
+size_t hals_panel_floats(int K, int tile) {
+  const int ntiles = (K + tile - 1) / tile;
+  return (size_t)ntiles * kpad(K) * tile + (size_t)ntiles * tile * tile;
+}
+
+bool hals_tile_supported(int K, int tile) {
+  if (tile == 32) return true;
+  if (tile != 16 && tile != 64) return false;
+  const int nt = (K + 31) / 32;
+  return K % 4 == 0 && rr_smem_floats(nt, tile) * 4 <= kRrLdsMax && (tile != 64 || nt <= 6);
 }
 
 hipError_t hals_update(const HalsArgs& a, hipStream_t s) {
@@ -1256,9 +1329,14 @@ hipError_t hals_update(const HalsArgs& a, hipStream_t s) {
   if (grid == 0 || a.K <= 0) return hipSuccess;
   if (a.K > kMaxK || !a.panel) return hipErrorInvalidValue;
   HalsArgs b = a;
-  b.gblk = a.panel + (int64_t)((a.K + T - 1) / T) * kpad(a.K) * T;
+  const int tile = a.tile ? a.tile : T;
+  if (!hals_tile_supported(a.K, tile)) return hipErrorInvalidValue;
+  b.tile = tile;
+  b.gblk = a.panel + (int64_t)((a.K + tile - 1) / tile) * kpad(a.K) * tile;
   const bool vec = (a.K % 4 == 0) && (((uintptr_t)a.X & 15) == 0);
-  if (h_rows_kernel_for(a.rows, a.K)) return h_rows_dispatch(b, vec, s);
+  if (tile != T && !vec) return hipErrorInvalidValue;
+  // widths other than 32: the rows-in-registers kernel only
+  if (tile != T || h_rows_kernel_for(a.rows, a.K)) return h_rows_dispatch(b, vec, s);
   const size_t bytes = h_smem_floats(a.K) * 4;
   const void* fn = vec ? (const void*)hals_h_kernel<true> : (const void*)hals_h_kernel<false>;
   hipError_t e = allow_smem(fn, bytes);

@@ -72,7 +72,8 @@ size_t gram_partial_floats(int K, int chunks);
 // from C (hals_panel_floats(K) floats; entries that never depend on C -- rows
 // >= K, and outside the last tile -- must have been zeroed once).
 hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, float* partial,
-                    int chunks, hipStream_t s, float* panel = nullptr, int diag_one = 0);
+                    int chunks, hipStream_t s, float* panel = nullptr, int diag_one = 0,
+                    int tile = 32);
 
 // ------------------------------------------------------------------ SpMM ----
 // out[r, 0:K] = sum_j val[j] X[col[j], 0:K] over the rows of a CSR matrix.
@@ -153,12 +154,16 @@ struct HalsArgs {
   int K;
   float eps;
   int diag_one;          // 1: H update (cdiag = 1 - G_tt); 0: no diagonal term
-  const float* panel;    // tile panels of G (gram_xtx with panel output, diag_one as here)
+  const float* panel;    // tile panels of G (gram_xtx with panel output, diag_one and tile as here)
   const float* gblk;     // set by hals_update
+  int tile;              // tile width: 32 (0 = 32), 16 or 64 (see hals_tile_supported)
 };
 // Row-independent update (no normalisation): the H half and fold-in.
 hipError_t hals_update(const HalsArgs& a, hipStream_t s);
-size_t hals_panel_floats(int K);
+size_t hals_panel_floats(int K, int tile = 32);
+// Tile widths of the H update: 32 always; 16 and 64 when K % 4 == 0 and the
+// rows-in-registers kernel's double-buffered panel fits the LDS.
+bool hals_tile_supported(int K, int tile);
 int hals_rows_per_group_h();
 
 constexpr int kWFlagCol = 1024;  // column-group flags follow the product-group flags

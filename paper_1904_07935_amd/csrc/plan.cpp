@@ -89,6 +89,10 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
   float* partial = c.take<float>(std::max<size_t>(part, 1));
   float* gpart = c.take<float>(gram_partial_floats((int)K, gram_max_chunks()));
   float* panel = c.take<float>(hals_panel_floats((int)K));
+  // the H update's panels, sized for every supported tile width
+  const size_t ph = std::max(std::max(hals_panel_floats((int)K, 16), hals_panel_floats((int)K, 32)),
+                             hals_panel_floats((int)K, 64));
+  float* panel_h = c.take<float>(ph);
   const int64_t resid_tiles = ((V + 127) / 128) * ((D + 127) / 128);
   const int red_n = (int)std::max<int64_t>(std::max<int64_t>(resid_tiles, 1024), 1);
   double* red = c.take<double>((size_t)red_n);
@@ -105,6 +109,8 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
     p->partial = partial;
     p->gram_part = gpart;
     p->panel = panel;
+    p->panel_h = panel_h;
+    p->panel_h_floats = ph;
     p->partial_floats = std::max<size_t>(part, 1);
     p->red = red;
     p->red_n = red_n;
@@ -230,8 +236,11 @@ int plnmf::device_check(int* dev, int* cus) {
 
 // ------------------------------------------------------- step launchers ----
 hipError_t plnmf::gram(nmf_plan_s* p, const float* X, int64_t rows, float* out, int panel_diag) {
+  // panel_diag 1: the H update's panels (its own buffer and tile width);
+  // 0: the W update's (32 wide)
+  float* panel = panel_diag == 1 ? p->panel_h : panel_diag == 0 ? p->panel : nullptr;
   return gram_xtx(X, rows, p->K, out, p->K, p->gram_part, gram_chunks(rows, p->cus), p->stream,
-                  panel_diag >= 0 ? p->panel : nullptr, panel_diag);
+                  panel, panel_diag, panel_diag == 1 ? p->h_tile : kTile);
 }
 
 namespace {
@@ -368,7 +377,8 @@ int half_h(nmf_plan_s* p) {
   a.K = p->K;
   a.eps = p->eps;
   a.diag_one = 1;
-  a.panel = p->panel;
+  a.panel = p->panel_h;
+  a.tile = p->h_tile;
   TIMED(p, NMF_STEP_UPDATE_H, hals_update(a, p->stream));
   p->pq_valid = false;
   return NMF_OK;
@@ -585,6 +595,13 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
   INITCHECK(hipMemsetAsync(p->slots, 0, kSlotWords * sizeof(unsigned long long), st));
   INITCHECK(hipMemsetAsync(p->w_flags, 0, kWFlagWords * sizeof(unsigned), st));
   INITCHECK(hipMemsetAsync(p->panel, 0, hals_panel_floats(K) * sizeof(float), st));
+  INITCHECK(hipMemsetAsync(p->panel_h, 0, p->panel_h_floats * sizeof(float), st));
+  // the H update's tile width: NMF_TILE_T = 16, 32 or 64 where supported, else 32
+  p->h_tile = kTile;
+  if (const char* e = getenv("NMF_TILE_T")) {
+    const int t = atoi(e);
+    if (hals_tile_supported(K, t)) p->h_tile = t;
+  }
   // input checks: W, Ht finite and non-negative; A structure and values
   INITCHECK(check_finite_nonneg(W, s.V * K, p->status, 1, st));
   INITCHECK(check_finite_nonneg(Ht, s.D * K, p->status, 2, st));
@@ -754,7 +771,7 @@ int nmf_plan_info(nmf_plan p, nmf_info* info) {
   info->K = p->K;
   info->format = p->fmt;
   info->precision = p->prec;
-  info->tile = kTile;
+  info->tile = p->h_tile;
   info->w_groups = p->w_groups;
   info->h_groups = (int)((p->D + hals_rows_per_group_h() - 1) / hals_rows_per_group_h());
   info->sweeps_done = p->sweeps_done;

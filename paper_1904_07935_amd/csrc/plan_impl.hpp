@@ -76,7 +76,10 @@ struct nmf_plan_s {
   float* P2 = nullptr;      // FP32 A H^T for the objective of BF16 plans
   float* partial = nullptr;
   float* gram_part = nullptr;   // per-chunk partial Grams
-  float* panel = nullptr;       // precomputed tile panels of the H update
+  float* panel = nullptr;       // precomputed tile panels of the W update (32 wide)
+  float* panel_h = nullptr;     // those of the H update (h_tile wide)
+  size_t panel_h_floats = 0;
+  int h_tile = 32;              // tile width of the H update
   size_t partial_floats = 0;
   double* colsq = nullptr;
   double* red = nullptr;
@@ -100,8 +103,8 @@ struct nmf_plan_s {
 };
 
 namespace plnmf {
-// out = X^T X; with panel_diag >= 0 also the column updates' tile panels
-// (p->panel) with that diagonal rule
+// out = X^T X; with panel_diag 1 also the H update's tile panels (p->panel_h,
+// p->h_tile wide), with 0 the W update's (p->panel, 32 wide)
 hipError_t gram(nmf_plan_s* p, const float* X, int64_t rows, float* out, int panel_diag = -1);
 int enqueue_objective(nmf_plan_s* p);
 // nmf_foldin on a given workspace (also serves the entry point that brings none)

@@ -59,3 +59,52 @@ def test_rows_kernel_full_sweeps_match_oracle(cuda, monkeypatch):
         ref.append(hals.objective(Ao, W, H)[1])
     ref = np.array(ref)
     assert np.max(np.abs(rel - ref) / ref) <= 1e-5
+
+
+@pytest.mark.parametrize("V,D,K", [(300, 1000, 40), (400, 900, 160), (700, 700, 400)])
+@pytest.mark.parametrize("tile", [16, 64])
+def test_tile_widths_match_oracle(cuda, monkeypatch, V, D, K, tile):
+    """NMF_TILE_T: the H update with 16- or 64-column tiles (the tile-size
+    study's kernels) against the untiled oracle -- the tiling only reorders
+    the sums (Alg. 2).  A width whose double-buffered panel does not fit the
+    LDS (64 at K = 400) falls back to 32, reported by the plan."""
+    monkeypatch.setenv("NMF_TILE_T", str(tile))
+    A = datagen.dense_planted_uniform(V, D, max(2, K // 2), 0.01, seed=D + K)
+    W0, H0 = datagen.uniform_init(V, D, K, seed=K + 1)
+    Ao = oracle_A(A)
+    H1, _, _ = hals.h_half(Ao, hals.normalize_columns(W0), H0, EPS)
+    plan = gpu_plan(A, W0, H0, cuda)
+    want = tile if (tile == 16 or K <= 160) else 32
+    assert plan.info()["tile"] == want
+    plan.half("H")
+    got = _np(plan.Ht).T
+    assert rel_fro(got, H1) < 1e-4
+    assert row_rms_max(got, H1) < 2e-4
+    rel = np.array(plan.sweep(3, objective=True))
+    assert np.all(np.isfinite(rel))
+    plan.close()
+
+
+def test_tile_width_in_foldin(cuda, monkeypatch):
+    """Fold-in (the H update with W fixed) at 16-column tiles against the oracle."""
+    import torch
+
+    from paper_1904_07935_amd.api import Matrix
+    monkeypatch.setenv("NMF_TILE_T", "16")
+    c = datagen.bag_of_words(2000, 900, 1.1, 77.0, 2)
+    K = 48
+    W0, H0 = datagen.uniform_init_matched(2000, 900, K, datagen.mean_value(c.A), 1)
+    plan = gpu_plan(c.A, W0, H0, cuda)
+    assert plan.info()["tile"] == 16
+    W = _np(plan.W)
+    new = datagen.bag_of_words_docs(500, 1.1, 77.0, 7, c.perm, c.idf)
+    _, Hn = datagen.uniform_init_matched(2000, 500, K, datagen.mean_value(new), 4)
+    Ht = torch.tensor(np.ascontiguousarray(Hn.T), device=cuda)
+    trace = plan.foldin(Matrix.from_csr(new, cuda), Ht, init="given", n_sweeps=10)
+    from tests.gpu_util import rows_csr_to_oracle
+    An = rows_csr_to_oracle(new)
+    rels = [hals.objective(An, W, Hn.astype(np.float64))[1]]
+    hals.foldin(An, W, Hn, EPS, 10, on_sweep=lambda i, H: rels.append(hals.objective(An, W, H)[1]))
+    d = np.abs(np.array(trace) - np.array(rels)) / np.array(rels)
+    assert d.max() <= 1e-5
+    plan.close()
