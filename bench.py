@@ -55,6 +55,9 @@ def parse(argv=None):
                          "its BF16-product form and the MU baseline (--config c1/c2/c4), "
                          "or cold/WTA/network-warm fold-in (--config c3)")
     ap.add_argument("--tto-sweeps", type=int, default=0)
+    ap.add_argument("--tile-study", action="store_true",
+                    help="time the H update for tile widths 16/32/64 at K = 80/160/240/400 "
+                         "(rows-in-registers kernel) beside the LDS/VGPR capacity model")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="afterwards, copy this many bytes device-to-device three times "
                          "(a kernel of known traffic for scaling HBM counters)")
@@ -495,6 +498,73 @@ def tto_foldin(args, dev):
     print(json.dumps(out), flush=True)
 
 
+# ----------------------------------------------------------- tile study ----
+
+LDS_BYTES = 160 * 1024
+MFMA_CYCLES = 64  # one 32x32x2 FP32 matrix-core product per SIMD
+
+
+def tile_model(K, T):
+    """Capacity and cost model of the rows-in-registers H update at tile width
+    T (the analogue of Sec. 5's model for this kernel).  Capacity: the
+    workgroup's LDS holds two panels of NB = max(1, T/32) x 32 ceil(K/32) rows
+    of 32 floats, two T x T G blocks and four 32 x max(T+1, 33) transposes; a
+    lane's VGPRs hold the 16 ceil(K/32) row values, NB accumulators and the
+    phase-2 columns (about 1.5 T / 2).  Cost per wave and tile: the product
+    takes 16 ceil(K/32) NB matrix-core steps of 64 cycles (a 16-wide tile
+    still runs a 32-wide product); phase 2 takes T column steps whose work
+    grows with the T/2 columns a lane updates.  Returns the LDS bytes, a VGPR
+    estimate, whether it fits, and the product and phase-2 cycles per sweep
+    of one wave (phase-2 step cost 40 + 4 T/2 cycles, an estimate)."""
+    nt = (K + 31) // 32
+    nb = max(1, T // 32)
+    lds = 4 * (2 * nb * nt * 1024 + 2 * T * T + 4 * 32 * max(T + 1, 33))
+    vgpr = 16 * nt + 32 * nb + 3 * T // 2 + 64
+    tiles = (K + T - 1) // T
+    prod = tiles * 16 * nt * nb * MFMA_CYCLES
+    ph2 = tiles * T * (40 + 4 * (T // 2))
+    return {"lds_bytes": lds, "vgpr_est": vgpr, "fits": lds <= LDS_BYTES and (T != 64 or nt <= 6),
+            "product_cycles": prod, "phase2_cycles": ph2, "model_cycles": prod + ph2}
+
+
+def tile_study(args, dev):
+    import numpy as np
+    import torch
+
+    import datagen
+    from paper_1904_07935_amd.api import Matrix, Plan
+
+    corpus = datagen.c4() if args.config == "c4" else datagen.c1()
+    A = corpus.A
+    M = Matrix.from_csr(A, dev)
+    rows = []
+    os.environ["NMF_H_KERNEL"] = "rows"
+    for K in (80, 160, 240, 400):
+        W0, H0 = datagen.uniform_init_matched(A.rows, A.cols, K, datagen.mean_value(A), 1)
+        for T in (16, 32, 64):
+            os.environ["NMF_TILE_T"] = str(T)
+            mod = tile_model(K, T)
+            W = torch.tensor(W0, device=dev)
+            Ht = torch.tensor(np.ascontiguousarray(H0.T), device=dev)
+            plan = Plan(M, W, Ht, eps=1e-16)
+            got = plan.info()["tile"]
+            us = None
+            if got == T:
+                plan.sweep(2)
+                plan.profile(True)
+                plan.sweep(5)
+                plan.profile(False)
+                ms, n = plan.profile_read()["update_H"]
+                us = 1000.0 * ms / max(n, 1)
+            plan.close()
+            rows.append({"K": K, "T": T, "update_H_us": None if us is None else round(us, 1),
+                         **mod})
+            print(f"[tile] K={K} T={T}: {us} us (fits {mod['fits']})", file=sys.stderr, flush=True)
+    del os.environ["NMF_TILE_T"], os.environ["NMF_H_KERNEL"]
+    print(json.dumps({"mode": "tile_study", "config": {"workload": args.config, "V": A.rows,
+                      "D": A.cols, "nnz": int(A.nnz)}, "rows": rows}), flush=True)
+
+
 # ----------------------------------------------------------------- main ----
 
 def main():
@@ -515,6 +585,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.tile_study:
+        tile_study(args, dev)
+        return
     if args.tto or args.config == "c3":
         if args.config == "c3":
             tto_foldin(args, dev)

@@ -10,7 +10,8 @@ import os
 from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_size_t, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libplnmf.so")
+# PLNMF_LIB points at another build of the same library (e.g. the sanitizer build)
+LIB_PATH = os.environ.get("PLNMF_LIB") or os.path.join(HERE, "libplnmf.so")
 
 NMF_OK = 0
 STATUS_NAMES = {0: "NMF_OK", -1: "NMF_E_ARG", -2: "NMF_E_SHAPE", -3: "NMF_E_WORKSPACE",

@@ -11,7 +11,7 @@ from ctypes import POINTER, byref, c_double, c_float, c_int, c_int32, c_int64, c
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libplnmf_cpu.so")
+LIB_PATH = os.environ.get("PLNMF_CPU_LIB") or os.path.join(HERE, "libplnmf_cpu.so")
 _lib = None
 
 
