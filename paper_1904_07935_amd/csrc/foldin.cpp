@@ -18,7 +18,7 @@ size_t mlp_ws_bytes(int K, int H, int64_t B);
 namespace {
 
 constexpr int kTraceChunk = 1024;
-constexpr int64_t kMlpBatch = 8192;
+constexpr int64_t kMlpBatch = 131072;  // rows per network inference pass
 
 struct FoldWs {
   float* R;       // [D',K]

@@ -69,11 +69,11 @@ __device__ __forceinline__ void epilogue(int epi, int64_t M, int64_t N, float* _
             ss += (double)e * (double)e;
           } else if (epi == EPI_BIAS_GELU) {
             const float z = v + bias[n];
-            C[m * ldc + n] = z;
+            if (C) C[m * ldc + n] = z;
             ((__bf16*)C2)[m * ldc + n] = (__bf16)gelu_f(z);
           } else if (epi == EPI_BIAS_SOFTPLUS) {
             const float z = v + bias[n];
-            C[m * ldc + n] = z;
+            if (C) C[m * ldc + n] = z;
             ((float*)C2)[m * ldc + n] = softplus_f(z);
           } else if (epi == EPI_GELU_GRAD) {
             const float d = v * gelu_grad_f(Dm[m * ldd + n]);

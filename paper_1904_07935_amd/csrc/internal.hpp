@@ -26,8 +26,8 @@ constexpr int kSlotWords = kSlotReplicas * kSlotStride;
 enum GemmEpi : int {
   EPI_STORE = 0,      // C = acc (+ bias[n])
   EPI_RESID_SQ = 1,   // red_out[tile] = sum (D - acc)^2 over the tile (FP64)
-  EPI_BIAS_GELU = 2,  // C = acc + bias (pre-activation, FP32); C2 (bf16) = GELU(C)
-  EPI_BIAS_SOFTPLUS = 3, // C = acc + bias (FP32); C2 (float) = softplus(C)
+  EPI_BIAS_GELU = 2,  // C = acc + bias (pre-activation, FP32; skipped if C is NULL); C2 (bf16) = GELU(C)
+  EPI_BIAS_SOFTPLUS = 3, // C = acc + bias (FP32; skipped if NULL); C2 (float) = softplus(C)
   EPI_GELU_GRAD = 4,  // C (FP32, if set) and C2 (bf16) = acc * GELU'(D), D = z1
   EPI_MU = 5,         // C = D * X / (acc + mu_delta), X = (const float*)C2 (ld = ldc);
                       // C may be D (each element is read, then written, by one thread)

@@ -248,20 +248,72 @@ int loss_grad_rows(const Params& p, int K, int H, const float* X, const float* Y
 
 namespace plnmf {
 // used by fold-in: forward over N rows in workspace-sized batches
+// Inference needs only the BF16 input and hidden activations (no FP32
+// pre-activations, no backward buffers): about (K + H) * 2 bytes per row.
+struct WsI {
+  __bf16* xb;  // [B, K]
+  __bf16* gb;  // [B, H]
+  size_t off;
+};
+WsI ws_infer_layout(void* base, int K, int H, int64_t B) {
+  Carver c(base);
+  WsI w;
+  w.xb = c.take<__bf16>((size_t)(B * K));
+  w.gb = c.take<__bf16>((size_t)(B * H));
+  c.take<char>(kAlign);
+  w.off = c.off;
+  return w;
+}
+int64_t batch_infer_of(int K, int H, size_t bytes) {
+  const size_t per = ws_infer_layout(nullptr, K, H, 2).off - ws_infer_layout(nullptr, K, H, 1).off;
+  const size_t f0 = ws_infer_layout(nullptr, K, H, 1).off;
+  if (bytes < f0) return 0;
+  int64_t b = 1 + (int64_t)((bytes - f0) / std::max<size_t>(per, 1));
+  while (b > 1 && ws_infer_layout(nullptr, K, H, b).off > bytes) b--;
+  return b;
+}
+
 int mlp_forward_impl(const void* params, int K, int H, const float* X, float* Y, int64_t N,
                      void* ws, size_t bytes, hipStream_t s) {
-  const int64_t B = batch_of(K, H, bytes);
+  const int64_t B = batch_infer_of(K, H, bytes);
   if (B < 1) return fail(NMF_E_WORKSPACE, "network workspace too small");
-  const Ws w = ws_layout(ws, K, H, B);
+  const WsI w = ws_infer_layout(ws, K, H, B);
   const Params p = view((void*)params, K, H);
   for (int64_t r = 0; r < N; r += B) {
     const int64_t b = std::min(B, N - r);
-    int rc = forward_rows(p, K, H, X + r * K, Y + r * K, b, w, s);
-    if (rc) return rc;
+    MLPCHECK(cast_bf16(X + r * K, w.xb, b * K, s));
+    GemmArgs g{};
+    g.A = w.xb;
+    g.lda = K;
+    g.B = p.W1b;  // B(k,j) = W1[j*K + k]
+    g.ldb = K;
+    g.M = b;
+    g.N = H;
+    g.Kd = K;
+    g.epi = EPI_BIAS_GELU;  // the pre-activation (C) is not kept
+    g.bias = p.b1;
+    g.C2 = w.gb;
+    g.ldc = H;
+    g.splits = 1;
+    MLPCHECK(gemm(Elem::BF16, false, true, g, s));
+    GemmArgs g2{};
+    g2.A = w.gb;
+    g2.lda = H;
+    g2.B = p.W2b;  // B(j,k) = W2[k*H + j]
+    g2.ldb = H;
+    g2.M = b;
+    g2.N = K;
+    g2.Kd = H;
+    g2.epi = EPI_BIAS_SOFTPLUS;
+    g2.bias = p.b2;
+    g2.C2 = Y + r * K;
+    g2.ldc = K;
+    g2.splits = 1;
+    MLPCHECK(gemm(Elem::BF16, false, true, g2, s));
   }
   return NMF_OK;
 }
-size_t mlp_ws_bytes(int K, int H, int64_t B) { return ws_layout(nullptr, K, H, B).off; }
+size_t mlp_ws_bytes(int K, int H, int64_t B) { return ws_infer_layout(nullptr, K, H, B).off; }
 }  // namespace plnmf
 
 extern "C" {

@@ -203,8 +203,9 @@ def test_adam_step_matches_oracle(cuda):
 def test_trained_warm_start_beats_cold_start(cuda):
     """The learned part's gain: trained on (normalised A^T W rows -> converged
     fold-in solutions) that HALS itself produced, the network's warm start needs
-    fewer H-only sweeps than the cold start to come within 1e-4 of the cold
-    start's converged relative objective on held-out documents."""
+    fewer H-only sweeps than both the cold start and the non-learned WTA start
+    (max(eps, A^T W)) to come within 1e-4 of the cold start's converged
+    relative objective on held-out documents."""
     import torch
 
     from paper_1904_07935_amd.api import Matrix, Mlp
@@ -238,13 +239,18 @@ def test_trained_warm_start_beats_cold_start(cuda):
     tr_cold = plan.foldin(Mev, cold(evald), init="given", n_sweeps=100)
     tr_mlp = plan.foldin(Mev, torch.zeros(evald.rows, K, device=cuda), init="mlp", mlp=net,
                          n_sweeps=100)
+    tr_wta = plan.foldin(Mev, torch.zeros(evald.rows, K, device=cuda), init="wta", n_sweeps=100)
 
-    def sweeps_to(tr):
-        hit = [i for i, v in enumerate(tr) if v <= target]
+    def sweeps_to(tr, gap=1e-4):
+        hit = [i for i, v in enumerate(tr) if v <= ref[-1] + gap]
         return hit[0] if hit else 10 ** 9
 
-    s_cold, s_mlp = sweeps_to(tr_cold), sweeps_to(tr_mlp)
-    print(f"sweeps to target: cold {s_cold}, mlp {s_mlp}; rel0 cold {tr_cold[0]:.5f} mlp {tr_mlp[0]:.5f}")
-    assert tr_mlp[0] < tr_cold[0]
-    assert s_mlp < s_cold
+    s_cold, s_mlp, s_wta = sweeps_to(tr_cold), sweeps_to(tr_mlp), sweeps_to(tr_wta)
+    print(f"sweeps to target: cold {s_cold}, wta {s_wta}, mlp {s_mlp}; rel0 cold {tr_cold[0]:.5f} "
+          f"wta {tr_wta[0]:.5f} mlp {tr_mlp[0]:.5f}")
+    for gap in (1e-5, 1e-6, 1e-7):
+        print(f"  within {gap:g}: cold {sweeps_to(tr_cold, gap)} wta {sweeps_to(tr_wta, gap)} "
+              f"mlp {sweeps_to(tr_mlp, gap)}")
+    assert tr_mlp[0] < tr_cold[0] and tr_mlp[0] < tr_wta[0]
+    assert s_mlp < s_cold and s_mlp < s_wta
     plan.close()
