@@ -101,7 +101,16 @@ int spmm_item_nnz(int64_t nnz);
 SpmmSizes spmm_sizes(int64_t rows, int64_t nnz, int L);
 // Copies the row pointers to the host, plans the items, uploads them
 // (synchronises the stream).  Device buffers must be sized by spmm_sizes.
-hipError_t spmm_build(SpmmPlan* p, hipStream_t s);
+// Rows r with skip[r] != 0 (host array, optional) that are longer than L get
+// no items: their output rows are left to the caller.
+hipError_t spmm_build(SpmmPlan* p, hipStream_t s, const uint8_t* skip = nullptr);
+// Dense copy of selected CSR rows: out[i][:] = row rows[i] of the CSR
+// (out [n, cols] zeroed first); and the scatter of product rows back:
+// dst[rows[i]][:] = src[i][:] (K columns).
+hipError_t csr_dense_rows(const int32_t* rowptr, const int32_t* col, const float* val,
+                          const int32_t* rows, int n, int64_t cols, float* out, hipStream_t s);
+hipError_t scatter_rows(const float* src, const int32_t* rows, int n, int K, float* dst,
+                        hipStream_t s);
 hipError_t spmm(const SpmmPlan& p, Elem t, const void* X, int K, float* out, hipStream_t s);
 // Columns [k0, k0 + K) only: out[r, k0 + c] = sum_j a[r, j] X[col_j, k0 + c],
 // X rows ldx apart, out rows ldo apart.

@@ -206,4 +206,39 @@ hipError_t combine_objective(const double* a2, const double* wp, const double* s
   return hipGetLastError();
 }
 
+
+namespace {
+__global__ void dense_rows_kernel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                  const float* __restrict__ val, const int32_t* __restrict__ rows,
+                                  int64_t cols, float* __restrict__ out) {
+  const int i = blockIdx.x;
+  const int64_t r = rows[i];
+  float* o = out + (int64_t)i * cols;
+  for (int64_t j = rowptr[r] + threadIdx.x; j < rowptr[r + 1]; j += blockDim.x) o[col[j]] = val[j];
+}
+
+__global__ void scatter_rows_kernel(const float* __restrict__ src, const int32_t* __restrict__ rows,
+                                    int K, float* __restrict__ dst) {
+  const int i = blockIdx.x;
+  const int64_t r = rows[i];
+  for (int c = threadIdx.x; c < K; c += blockDim.x) dst[r * K + c] = src[(int64_t)i * K + c];
+}
+}  // namespace
+
+hipError_t csr_dense_rows(const int32_t* rowptr, const int32_t* col, const float* val,
+                          const int32_t* rows, int n, int64_t cols, float* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e = hipMemsetAsync(out, 0, (size_t)n * cols * sizeof(float), s);
+  if (e != hipSuccess) return e;
+  dense_rows_kernel<<<(unsigned)n, 256, 0, s>>>(rowptr, col, val, rows, cols, out);
+  return hipGetLastError();
+}
+
+hipError_t scatter_rows(const float* src, const int32_t* rows, int n, int K, float* dst,
+                        hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  scatter_rows_kernel<<<(unsigned)n, 128, 0, s>>>(src, rows, K, dst);
+  return hipGetLastError();
+}
+
 }  // namespace plnmf

@@ -86,6 +86,8 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
     need(D, K, V);
     need(V, K, D);
   }
+  const bool dense_rows = s.fmt == NMF_CSR && s.prec == NMF_FP32;
+  if (dense_rows) need(kDenseRowsMax, K, D);
   float* partial = c.take<float>(std::max<size_t>(part, 1));
   float* gpart = c.take<float>(gram_partial_floats((int)K, gram_max_chunks()));
   float* panel = c.take<float>(hals_panel_floats((int)K));
@@ -135,6 +137,13 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
     int32_t* slT = c.take<int32_t>((size_t)zT.items);
     int32_t* fixT = c.take<int32_t>((size_t)(3 * zT.fix));
     float* carryT = c.take<float>((size_t)(zT.seg * K));
+    float *a_top = nullptr, *c_top = nullptr;
+    int32_t* top_idx = nullptr;
+    if (s.prec == NMF_FP32) {
+      a_top = c.take<float>((size_t)kDenseRowsMax * D);
+      c_top = c.take<float>((size_t)kDenseRowsMax * K);
+      top_idx = c.take<int32_t>((size_t)kDenseRowsMax);
+    }
     __bf16 *avb = nullptr, *tvb = nullptr, *xb = nullptr;
     float* P2 = nullptr;
     if (s.prec == NMF_BF16_PRODUCTS) {
@@ -156,6 +165,9 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
       p->sp_At.item_slot = slT;
       p->sp_At.fix = fixT;
       p->sp_At.carry = carryT;
+      p->a_top = a_top;
+      p->c_top = c_top;
+      p->top_idx = top_idx;
       p->a_val_bf = avb;
       p->t_val_bf = tvb;
       p->X_bf = xb;
@@ -281,6 +293,15 @@ hipError_t product_R(nmf_plan_s* p) {
   return gemm(Elem::F32, true, false, g, p->stream);
 }
 
+// NMF_DENSE_ROWS=0 keeps every row of A in the sparse P product, =1 takes the
+// dense rows whatever the size (measurement, tests); unset: by size.
+int dense_rows_mode() {
+  const char* e = getenv("NMF_DENSE_ROWS");
+  if (e && e[0] == '0') return 0;
+  if (e && e[0] == '1') return 1;
+  return -1;
+}
+
 // P = A H^T  (V x K), from Ht [D,K]
 hipError_t product_P(nmf_plan_s* p, bool force_fp32, float* out) {
   const int K = p->K;
@@ -291,8 +312,26 @@ hipError_t product_P(nmf_plan_s* p, bool force_fp32, float* out) {
       if (e != hipSuccess) return e;
       return spmm(p->sp_A, Elem::BF16, p->X_bf, K, out, p->stream);
     }
-    return spmm(p->prec == NMF_BF16_PRODUCTS ? p->sp_A_f32 : p->sp_A, Elem::F32, p->Ht, K, out,
-                p->stream);
+    if (p->prec == NMF_BF16_PRODUCTS) return spmm(p->sp_A_f32, Elem::F32, p->Ht, K, out, p->stream);
+    hipError_t e = spmm(p->sp_A, Elem::F32, p->Ht, K, out, p->stream);
+    if (e != hipSuccess || p->n_top == 0) return e;
+    // the dense rows: C_top [n_top, K] = A_top [n_top, D] H^T, then into their rows of P
+    GemmArgs g{};
+    g.A = p->a_top;
+    g.lda = p->D;
+    g.B = p->Ht;  // B(d,k) = Ht[d*K + k]
+    g.ldb = K;
+    g.M = p->n_top;
+    g.N = K;
+    g.Kd = p->D;
+    g.C = p->c_top;
+    g.ldc = K;
+    g.epi = EPI_STORE;
+    g.splits = gemm_pick_splits(g.M, g.N, g.Kd, &g.k_per_split);
+    g.partial = p->partial;
+    e = gemm(Elem::F32, false, false, g, p->stream);
+    if (e != hipSuccess) return e;
+    return scatter_rows(p->c_top, p->top_idx, p->n_top, K, out, p->stream);
   }
   GemmArgs g{};
   g.M = p->V;
@@ -637,7 +676,42 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
     p->sp_At.rowptr = p->t_rowptr;
     p->sp_At.col = p->t_col;
     p->sp_At.val = p->t_val;
-    INITCHECK(spmm_build(&p->sp_A, st));
+    std::vector<uint8_t> skip;
+    const int drm = dense_rows_mode();
+    if (precision == NMF_FP32 && (drm == 1 || (drm < 0 && s.D * (int64_t)K >= kDenseRowsMinDK))) {
+      // the densest rows of A (longer than one work item and at least 1/16
+      // dense; at most kDenseRowsMax, longest first) are multiplied as a dense
+      // block on the matrix cores; the sparse product skips them.  Only when
+      // H^T is large (D K >= 32M floats): then each gathered row mostly comes
+      // from HBM, and the dense block reads H^T once instead; for a smaller
+      // H^T the gathers hit the caches and the split-K product costs more
+      // than it saves (measured: 26,000 x 11,000 at K = 200, P 82 -> 147 us)
+      std::vector<int32_t> rp((size_t)s.V + 1);
+      INITCHECK(hipMemcpyAsync(rp.data(), A->rowptr, rp.size() * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, st));
+      INITCHECK(hipStreamSynchronize(st));
+      std::vector<int32_t> cand;
+      for (int64_t r = 0; r < s.V; r++) {
+        const int64_t len = (int64_t)rp[r + 1] - rp[r];
+        if (len > p->sp_A.L && len * 16 >= s.D) cand.push_back((int32_t)r);
+      }
+      std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
+        return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+      });
+      if ((int)cand.size() > kDenseRowsMax) cand.resize(kDenseRowsMax);
+      std::sort(cand.begin(), cand.end());
+      p->n_top = (int)cand.size();
+      if (p->n_top > 0) {
+        skip.assign((size_t)s.V, 0);
+        for (int32_t r : cand) skip[r] = 1;
+        INITCHECK(hipMemcpyAsync(p->top_idx, cand.data(), cand.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st));
+        INITCHECK(csr_dense_rows(A->rowptr, A->colidx, A->values, p->top_idx, p->n_top, s.D,
+                                 p->a_top, st));
+        INITCHECK(hipStreamSynchronize(st));  // cand is a host buffer
+      }
+    }
+    INITCHECK(spmm_build(&p->sp_A, st, skip.empty() ? nullptr : skip.data()));
     INITCHECK(spmm_build(&p->sp_At, st));
     if (precision == NMF_BF16_PRODUCTS) {
       p->sp_A_f32 = p->sp_A;

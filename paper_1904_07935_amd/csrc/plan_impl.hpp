@@ -25,6 +25,8 @@ int fail(int code, const char* fmt, ...);
   } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int kDenseRowsMax = 128;  // rows of A multiplied as a dense block in P = A H^T
+constexpr int64_t kDenseRowsMinDK = (int64_t)32 << 20;  // ... when D K reaches this
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Sequential carve of a workspace: with base == nullptr it only sizes.
@@ -68,6 +70,10 @@ struct nmf_plan_s {
   __bf16* X_bf = nullptr;   // per-sweep BF16 cast of W or Ht
   plnmf::SpmmPlan sp_A{}, sp_At{};
   plnmf::SpmmPlan sp_A_f32{};  // FP32 values of A (objective of BF16 plans)
+  float* a_top = nullptr;       // [n_top, D] the densest rows of A, dense (FP32 CSR plans)
+  float* c_top = nullptr;       // [n_top, K] their rows of P
+  int32_t* top_idx = nullptr;   // [n_top] their row indices
+  int n_top = 0;
   float* P = nullptr;
   float* Q = nullptr;
   float* R = nullptr;

@@ -366,7 +366,7 @@ SpmmSizes spmm_sizes(int64_t rows, int64_t nnz, int L) {
   return z;
 }
 
-hipError_t spmm_build(SpmmPlan* p, hipStream_t s) {
+hipError_t spmm_build(SpmmPlan* p, hipStream_t s, const uint8_t* skip) {
   const int64_t rows = p->rows;
   const int L = p->L;
   std::vector<int32_t> rp((size_t)rows + 1);
@@ -381,6 +381,10 @@ hipError_t spmm_build(SpmmPlan* p, hipStream_t s) {
   int64_t r = 0;
   while (r < rows) {
     const int64_t len = (int64_t)rp[r + 1] - rp[r];
+    if (len > L && skip && skip[r]) {  // a long row computed elsewhere: no items
+      r++;
+      continue;
+    }
     if (len > L) {  // a long row: segments of L nonzeros, summed by the fixup pass
       const int32_t first = nseg;
       int32_t cnt = 0;

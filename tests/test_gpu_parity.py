@@ -366,3 +366,27 @@ def test_timeout_reported_by_sweep_without_objective(cuda):
         plan.sweep(0)
     assert e.value.status == -7
     plan.close()
+
+
+@pytest.mark.parametrize("K", [16, 200])
+def test_dense_rows_in_p_product(cuda, monkeypatch, K):
+    """The densest rows of A (the Zipf head) multiplied as a dense block on the
+    matrix cores and scattered into P, the rest by the sparse product
+    (NMF_DENSE_ROWS=1 forces it at this size): P element by element and ten
+    sweeps' objectives against the oracle."""
+    monkeypatch.setenv("NMF_DENSE_ROWS", "1")
+    c = small_bow()
+    lens = np.diff(c.A.rowptr)
+    assert np.sum((lens > 128) & (16 * lens >= c.A.cols)) >= 3  # several rows qualify
+    W0, H0 = sparse_init(c, K)
+    plan = gpu_plan(c.A, W0, H0, cuda)
+    Ao = oracle_A(c.A)
+    plan.half("W")
+    P = np.asarray(Ao @ H0.astype(np.float32).astype(np.float64).T)
+    assert elem_rel_max(_np(plan.intermediates()["P"]), P) < 1e-4
+    plan.close()
+    plan = gpu_plan(c.A, W0, H0, cuda)
+    rel = np.array(plan.sweep(10, objective=True))
+    rel_or, _ = oracle_run(c.A, W0, H0, 10)
+    assert np.max(np.abs(rel - rel_or) / np.array(rel_or)) <= 1e-5
+    plan.close()
