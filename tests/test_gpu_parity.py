@@ -371,9 +371,10 @@ def test_timeout_reported_by_sweep_without_objective(cuda):
 @pytest.mark.parametrize("K", [16, 200])
 def test_dense_rows_in_p_product(cuda, monkeypatch, K):
     """The densest rows of A (the Zipf head) multiplied as a dense block on the
-    matrix cores and scattered into P, the rest by the sparse product
-    (NMF_DENSE_ROWS=1 forces it at this size): P element by element and ten
-    sweeps' objectives against the oracle."""
+    matrix cores -- scattered into P, and added into R from the rows of W they
+    name -- the rest by the sparse products (NMF_DENSE_ROWS=1 forces it at
+    this size): R and P element by element and ten sweeps' objectives against
+    the oracle."""
     monkeypatch.setenv("NMF_DENSE_ROWS", "1")
     c = small_bow()
     lens = np.diff(c.A.rowptr)
@@ -381,6 +382,11 @@ def test_dense_rows_in_p_product(cuda, monkeypatch, K):
     W0, H0 = sparse_init(c, K)
     plan = gpu_plan(c.A, W0, H0, cuda)
     Ao = oracle_A(c.A)
+    plan.half("H")  # R = A^T W: the dense rows' share added by the matrix cores
+    R = np.asarray(Ao.T @ hals.normalize_columns(W0))
+    assert elem_rel_max(_np(plan.intermediates()["R"]), R) < 1e-4
+    plan.close()
+    plan = gpu_plan(c.A, W0, H0, cuda)
     plan.half("W")
     P = np.asarray(Ao @ H0.astype(np.float32).astype(np.float64).T)
     assert elem_rel_max(_np(plan.intermediates()["P"]), P) < 1e-4
