@@ -25,9 +25,11 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
-# The W kernel keeps a 32-column tile per row in registers: its column loop
-# must unroll fully (static register indices), past the default size limit.
-EXTRA = {"hals.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+# The W kernel keeps a 32-column tile per row in registers, and the GEMM's
+# epilogue walks its accumulator blocks: both loops must unroll fully (static
+# register indices, no private-memory copy), past the default size limit.
+_FULL_UNROLL = ["-mllvm", "-pragma-unroll-threshold=1000000"]
+EXTRA = {"hals.hip": _FULL_UNROLL, "gemm.hip": _FULL_UNROLL}
 
 
 def sources():

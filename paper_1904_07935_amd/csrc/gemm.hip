@@ -15,6 +15,7 @@
 //         B[8(l/32)..+7][l%32] -> LDS k-contiguous: As[m][k], Bs[n][k]; BK = 32
 // Output block layout (both): lane l holds C[8j + 4(l/32) + i][l%32], j,i < 4.
 // Split-K writes FP32 partials that a fixed-order pass sums (deterministic).
+#include <cmath>
 #include <type_traits>
 
 #include "internal.hpp"
@@ -23,6 +24,26 @@ namespace plnmf {
 namespace {
 
 constexpr int BM = 128, BN = 128;
+
+// Operand tiles are read through buffer descriptors whose base is the step's
+// tile origin.  A lane whose element lies outside the matrix (a row past M or
+// N, a term past the end of its split) uses an offset past the descriptor's
+// range, and the hardware returns zeros for it without touching memory: no
+// branches, so the loads of a step issue back to back and the wait before the
+// LDS store counts them exactly.  Valid offsets stay below 2^31 bytes (the
+// host routes leading dimensions of 2^22 or more to the scalar path).
+constexpr uint32_t kOutside = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_view(const void* base, int64_t bytes) {
+  const int64_t n = bytes < 0 ? 0 : (bytes > 0x7fffffff ? 0x7fffffff : bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)n, 0x00020000);
+}
+__device__ __forceinline__ floatx4 ld4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(floatx4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ bf16x8 ld8h(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
 
 __device__ __forceinline__ float gelu_f(float z) {
   return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
@@ -45,7 +66,8 @@ __device__ __forceinline__ void epilogue(int epi, int64_t M, int64_t N, float* _
                                          void* __restrict__ C2, float* C,
                                          int64_t ldc, double* __restrict__ red_out,
                                          floatx16 (&acc)[2][2], int64_t r0, int64_t c0,
-                                         double* red_smem, bool mirror, float mu_delta) {
+                                         double* red_smem, bool mirror, float mu_delta,
+                                         int64_t red_slot) {
   const int lane = threadIdx.x & 63;
   double ss = 0.0;
 #pragma unroll
@@ -91,9 +113,25 @@ __device__ __forceinline__ void epilogue(int epi, int64_t M, int64_t N, float* _
     __syncthreads();
     if (threadIdx.x == 0) {
       const double t = red_smem[0] + red_smem[1] + red_smem[2] + red_smem[3];
-      red_out[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
+      red_out[red_slot] = t;
     }
   }
+}
+
+// XCD-aware tile order.  Workgroups go to the eight XCDs round robin by
+// linear id; this maps the ids that land on one XCD to a contiguous run of
+// tiles, N-tile fastest, so the tiles that share an A row block (and, for a
+// split, a B block) run on the same XCD and find it in that XCD's L2.  A
+// bijection on [0, tiles) whatever the dispatch order.
+__device__ __forceinline__ void tile_of(int& tx, int& ty, int& tz) {
+  const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+  const unsigned total = gx * gy * gz;
+  const unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned xcd = lin & 7, q = lin >> 3, per = total >> 3, rem = total & 7;
+  const unsigned t = xcd < rem ? xcd * (per + 1) + q : rem * (per + 1) + (xcd - rem) * per + q;
+  ty = (int)(t % gy);
+  tx = (int)((t / gy) % gx);
+  tz = (int)(t / (gx * gy));
 }
 
 // Global -> register -> LDS staging of one K-step of the A and B tiles.
@@ -108,28 +146,37 @@ struct Stage<float, AT, BT, VEC, 16> {
   float sa[8], sb[8];
   __device__ __forceinline__ void load(const float* __restrict__ A, const float* __restrict__ B,
                                        int64_t lda, int64_t ldb, int64_t M, int64_t N,
-                                       int64_t m0, int64_t n0, int64_t k0, int64_t ke, int tid) {
+                                       int64_t m0, int64_t n0, int64_t k0, int64_t ke, int64_t Kd,
+                                       int tid) {
     if constexpr (VEC) {
+      // this step's tile origin in each operand (wave-uniform), and the bytes
+      // from there to the operand's last element
+      const int64_t a0 = AT ? k0 * lda + m0 : m0 * lda + k0;
+      const int64_t b0 = BT ? n0 * ldb + k0 : k0 * ldb + n0;
+      const int64_t a_end = AT ? (Kd - 1) * lda + M : (M - 1) * lda + Kd;
+      const int64_t b_end = BT ? (N - 1) * ldb + Kd : (Kd - 1) * ldb + N;
+      const __amdgpu_buffer_rsrc_t va = tile_view(A + a0, (a_end - a0) * 4);
+      const __amdgpu_buffer_rsrc_t vb = tile_view(B + b0, (b_end - b0) * 4);
 #pragma unroll
       for (int p = 0; p < 2; p++) {
         const int idx = tid + 256 * p;
         if constexpr (!AT) {  // along k
           const int ml = idx >> 2, kq = idx & 3;
-          const int64_t m = m0 + ml, k = k0 + 4 * kq;
-          ra[p] = (m < M && k < ke) ? *(const floatx4*)(A + m * lda + k) : floatx4{0, 0, 0, 0};
+          const bool ok = m0 + ml < M && k0 + 4 * kq < ke;
+          ra[p] = ld4(va, ok ? (uint32_t)(ml * lda + 4 * kq) * 4u : kOutside);
         } else {  // along m
           const int kl = idx >> 5, mq = idx & 31;
-          const int64_t m = m0 + 4 * mq, k = k0 + kl;
-          ra[p] = (m < M && k < ke) ? *(const floatx4*)(A + k * lda + m) : floatx4{0, 0, 0, 0};
+          const bool ok = m0 + 4 * mq < M && k0 + kl < ke;
+          ra[p] = ld4(va, ok ? (uint32_t)(kl * lda + 4 * mq) * 4u : kOutside);
         }
         if constexpr (!BT) {  // along n
           const int kl = idx >> 5, nq = idx & 31;
-          const int64_t n = n0 + 4 * nq, k = k0 + kl;
-          rb[p] = (n < N && k < ke) ? *(const floatx4*)(B + k * ldb + n) : floatx4{0, 0, 0, 0};
+          const bool ok = n0 + 4 * nq < N && k0 + kl < ke;
+          rb[p] = ld4(vb, ok ? (uint32_t)(kl * ldb + 4 * nq) * 4u : kOutside);
         } else {  // along k
           const int nl = idx >> 2, kq = idx & 3;
-          const int64_t n = n0 + nl, k = k0 + 4 * kq;
-          rb[p] = (n < N && k < ke) ? *(const floatx4*)(B + n * ldb + k) : floatx4{0, 0, 0, 0};
+          const bool ok = n0 + nl < N && k0 + 4 * kq < ke;
+          rb[p] = ld4(vb, ok ? (uint32_t)(nl * ldb + 4 * kq) * 4u : kOutside);
         }
       }
     } else {
@@ -186,29 +233,35 @@ struct Stage<__bf16, AT, BT, VEC, 32> {
   __bf16 sa[16], sb[16];
   __device__ __forceinline__ void load(const __bf16* __restrict__ A, const __bf16* __restrict__ B,
                                        int64_t lda, int64_t ldb, int64_t M, int64_t N,
-                                       int64_t m0, int64_t n0, int64_t k0, int64_t ke, int tid) {
-    const bf16x8 zero8 = {};
+                                       int64_t m0, int64_t n0, int64_t k0, int64_t ke, int64_t Kd,
+                                       int tid) {
     if constexpr (VEC) {
+      const int64_t a0 = AT ? k0 * lda + m0 : m0 * lda + k0;
+      const int64_t b0 = BT ? n0 * ldb + k0 : k0 * ldb + n0;
+      const int64_t a_end = AT ? (Kd - 1) * lda + M : (M - 1) * lda + Kd;
+      const int64_t b_end = BT ? (N - 1) * ldb + Kd : (Kd - 1) * ldb + N;
+      const __amdgpu_buffer_rsrc_t va = tile_view(A + a0, (a_end - a0) * 2);
+      const __amdgpu_buffer_rsrc_t vb = tile_view(B + b0, (b_end - b0) * 2);
 #pragma unroll
       for (int p = 0; p < 2; p++) {
         const int idx = tid + 256 * p;
         if constexpr (!AT) {
           const int ml = idx >> 2, kq = idx & 3;
-          const int64_t m = m0 + ml, k = k0 + 8 * kq;
-          ra[p] = (m < M && k < ke) ? *(const bf16x8*)(A + m * lda + k) : zero8;
+          const bool ok = m0 + ml < M && k0 + 8 * kq < ke;
+          ra[p] = ld8h(va, ok ? (uint32_t)(ml * lda + 8 * kq) * 2u : kOutside);
         } else {
           const int kl = idx >> 4, mq = idx & 15;
-          const int64_t m = m0 + 8 * mq, k = k0 + kl;
-          ra[p] = (m < M && k < ke) ? *(const bf16x8*)(A + k * lda + m) : zero8;
+          const bool ok = m0 + 8 * mq < M && k0 + kl < ke;
+          ra[p] = ld8h(va, ok ? (uint32_t)(kl * lda + 8 * mq) * 2u : kOutside);
         }
         if constexpr (!BT) {
           const int kl = idx >> 4, nq = idx & 15;
-          const int64_t n = n0 + 8 * nq, k = k0 + kl;
-          rb[p] = (n < N && k < ke) ? *(const bf16x8*)(B + k * ldb + n) : zero8;
+          const bool ok = n0 + 8 * nq < N && k0 + kl < ke;
+          rb[p] = ld8h(vb, ok ? (uint32_t)(kl * ldb + 8 * nq) * 2u : kOutside);
         } else {
           const int nl = idx >> 2, kq = idx & 3;
-          const int64_t n = n0 + nl, k = k0 + 8 * kq;
-          rb[p] = (n < N && k < ke) ? *(const bf16x8*)(B + n * ldb + k) : zero8;
+          const bool ok = n0 + nl < N && k0 + 8 * kq < ke;
+          rb[p] = ld8h(vb, ok ? (uint32_t)(nl * ldb + 8 * kq) * 2u : kOutside);
         }
       }
     } else {
@@ -303,65 +356,52 @@ struct Mfma<__bf16> {
 
 // Main loop: two register stages and two LDS buffers.  The global load of
 // K-step k + 2 is issued before computing step k and stored to LDS after
-// computing step k + 1, so each load has two compute steps to arrive.
+// computing step k + 1, so each load has two compute steps to arrive.  The
+// loop body is a pair of steps (an odd count gets one step of zeros).
 //
-// Two-level accumulation: the matrix cores accumulate Flush::steps K-steps into a
-// fresh accumulator, which is then added to the running total.  A single
-// accumulator chain over a contraction of n terms carries a rounding error
-// that grows like sqrt(n) units of FP32 rounding; with chunks of c terms the
-// chain is n / c long (c = 64 for FP32), which cuts the error of the
-// 800 - 10^4 term products several times at the cost of 64 adds per chunk.
-template <typename T>
-struct Flush {
-  static constexpr int steps = 4;  // K-steps per chunk: 64 (FP32) or 128 (BF16) terms
-};
-
-__device__ __forceinline__ void flush_acc(floatx16 (&tot)[2][2], floatx16 (&acc)[2][2]) {
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++) {
-      tot[i][j] += acc[i][j];
-#pragma unroll
-      for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
-    }
-}
-
+// Two-level accumulation: the matrix cores accumulate each pair of K-steps
+// (32 terms in FP32, 64 in BF16) into a fresh accumulator, which is then added
+// to the running total.  A single accumulator chain over a contraction of n
+// terms carries a rounding error that grows like sqrt(n) units of FP32
+// rounding; with chunks of c terms the chain is n / c long, which cuts the
+// error of the 800 - 10^4 term products several times.  A chunk per loop
+// iteration keeps the fresh accumulator local to the body, so it stays in
+// the matrix-core registers instead of moving through the VALU every step.
 template <typename T, typename St, typename TA, typename TB>
 __device__ __forceinline__ void pipeline(TA As, TB Bs, const T* __restrict__ A,
                                          const T* __restrict__ B, int64_t lda, int64_t ldb,
-                                         int64_t M, int64_t N, int64_t m0, int64_t n0, int64_t kb,
-                                         int64_t ke, int nk, int tid, floatx16 (&tot)[2][2], int wm,
-                                         int wn, int lane) {
+                                         int64_t M, int64_t N, int64_t Kd, int64_t m0, int64_t n0,
+                                         int64_t kb, int64_t ke, int nk, int tid,
+                                         floatx16 (&tot)[2][2], int wm, int wn, int lane) {
   constexpr int BK = Mfma<T>::BK;
-  static_assert(Flush<T>::steps % 2 == 0, "a chunk is whole loop iterations");
-  floatx16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; i++)
-#pragma unroll
-    for (int j = 0; j < 2; j++)
-#pragma unroll
-      for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+  if (nk <= 0) return;
   St s0, s1;
-  if (nk > 0) s0.load(A, B, lda, ldb, M, N, m0, n0, kb, ke, tid);
-  if (nk > 1) s1.load(A, B, lda, ldb, M, N, m0, n0, kb + BK, ke, tid);
-  if (nk > 0) {
+  s0.load(A, B, lda, ldb, M, N, m0, n0, kb, ke, Kd, tid);
+  s1.load(A, B, lda, ldb, M, N, m0, n0, kb + BK, ke, Kd, tid);
+  s0.store(As[0], Bs[0], tid);
+  __syncthreads();
+#pragma unroll 1
+  for (int kt = 0; kt < nk; kt += 2) {
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+      for (int j = 0; j < 2; j++)
+#pragma unroll
+        for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+    s0.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 2) * BK, ke, Kd, tid);
+    Mfma<T>::step(As[0], Bs[0], acc, wm, wn, lane);
+    s1.store(As[1], Bs[1], tid);
+    __syncthreads();
+    s1.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 3) * BK, ke, Kd, tid);
+    Mfma<T>::step(As[1], Bs[1], acc, wm, wn, lane);
     s0.store(As[0], Bs[0], tid);
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+      for (int j = 0; j < 2; j++) tot[i][j] += acc[i][j];
   }
-  for (int kt = 0; kt < nk; kt += 2) {
-    if (kt + 2 < nk) s0.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 2) * BK, ke, tid);
-    Mfma<T>::step(As[0], Bs[0], acc, wm, wn, lane);
-    if (kt + 1 < nk) s1.store(As[1], Bs[1], tid);
-    __syncthreads();
-    if (kt + 1 >= nk) break;
-    if (kt + 3 < nk) s1.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 3) * BK, ke, tid);
-    Mfma<T>::step(As[1], Bs[1], acc, wm, wn, lane);
-    if (kt + 2 < nk) s0.store(As[0], Bs[0], tid);
-    __syncthreads();
-    if ((kt + 2) % Flush<T>::steps == 0) flush_acc(tot, acc);
-  }
-  flush_acc(tot, acc);
 }
 
 template <typename T, bool AT, bool BT, bool VEC>
@@ -375,13 +415,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   const int splits = g.splits;
   const int64_t kps = g.k_per_split;
   const int sym = g.sym;
-  if (sym && blockIdx.y < blockIdx.x) return;  // symmetric product: upper tiles only
+  int tx, ty, tz;
+  tile_of(tx, ty, tz);
+  if (sym && ty < tx) return;  // symmetric product: upper tiles only
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t m0 = (int64_t)tx * BM, n0 = (int64_t)ty * BN;
   int64_t kb = 0, ke = Kd;
   if (splits > 1) {
-    kb = (int64_t)blockIdx.z * kps;
+    kb = (int64_t)tz * kps;
     ke = kb + kps < Kd ? kb + kps : Kd;
   }
   const int nk = (int)((ke - kb + BK - 1) / BK);
@@ -397,17 +439,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g) {
   if constexpr (std::is_same<T, float>::value) {
     __shared__ float As[2][BK][St::LDS_A];
     __shared__ float Bs[2][BK][St::LDS_B];
-    pipeline<T, St>(As, Bs, A, B, lda, ldb, M, N, m0, n0, kb, ke, nk, tid, acc, wm, wn, lane);
+    pipeline<T, St>(As, Bs, A, B, lda, ldb, M, N, Kd, m0, n0, kb, ke, nk, tid, acc, wm, wn, lane);
   } else {
     __shared__ __bf16 As[2][BM][St::LDS_K];
     __shared__ __bf16 Bs[2][BN][St::LDS_K];
-    pipeline<T, St>(As, Bs, A, B, lda, ldb, M, N, m0, n0, kb, ke, nk, tid, acc, wm, wn, lane);
+    pipeline<T, St>(As, Bs, A, B, lda, ldb, M, N, Kd, m0, n0, kb, ke, nk, tid, acc, wm, wn, lane);
   }
   const bool split = splits > 1;
-  float* out = split ? g.partial + (int64_t)blockIdx.z * M * N : g.C;
+  float* out = split ? g.partial + (int64_t)tz * M * N : g.C;
   epilogue(g.epi, M, N, out, split ? N : g.ldc, split, g.bias, g.D, g.ldd, g.C2, g.C, g.ldc,
            g.red_out, acc, m0 + wm * 64, n0 + wn * 64, red,
-           sym && !split && blockIdx.y != blockIdx.x, g.mu_delta);
+           sym && !split && ty != tx, g.mu_delta, (int64_t)ty * gridDim.x + tx);
 }
 
 __global__ void splitk_reduce_kernel(const float* __restrict__ partial, int splits, int64_t M,
@@ -430,14 +472,35 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 }  // namespace
 
+// Split-K choice: the estimated time of `s` splits is the number of rounds of
+// workgroups over the chip's slots (256 CUs, two workgroups each) times the
+// matrix-core time of one split's share of the contraction, plus the HBM time
+// of writing and summing the s partial products.  Every split keeps at least
+// 256 terms of the contraction.
 int gemm_pick_splits(int64_t M, int64_t N, int64_t Kd, int64_t* k_per_split) {
   const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  int splits = 1;
-  // aim for >= 512 workgroups while every split keeps >= 256 of the contraction
-  while (tiles * splits < 512 && Kd / (splits * 2) >= 256 && splits < 256) splits *= 2;
-  int64_t kps = (Kd + splits - 1) / splits;
+  constexpr double kSlots = 512.0;
+  constexpr double kTermSec = 2.0 * BM * BN / 307.2e9;  // one term of a tile, FP32 rate per slot
+  constexpr double kBytesPerSec = 4.0e12;
+  int best = 1;
+  double best_t = 0.0;
+  for (int s = 1; s <= 64; s++) {
+    if (s > 1 && Kd / s < 256) break;
+    int64_t kps = (Kd + s - 1) / s;
+    kps = (kps + 31) / 32 * 32;
+    const int real = (int)((Kd + kps - 1) / kps);
+    if (real != s) continue;
+    const double rounds = std::ceil((double)(tiles * s) / kSlots);
+    double t = rounds * (double)kps * kTermSec;
+    if (s > 1) t += (2.0 * s + 1.0) * (double)M * (double)N * 4.0 / kBytesPerSec;
+    if (s == 1 || t < best_t * 0.97) {  // a split must pay for itself
+      best = s;
+      best_t = t;
+    }
+  }
+  int64_t kps = (Kd + best - 1) / best;
   kps = (kps + 31) / 32 * 32;  // a multiple of both BK values
-  splits = (int)((Kd + kps - 1) / kps);
+  const int splits = (int)((Kd + kps - 1) / kps);
   if (k_per_split) *k_per_split = kps;
   return splits;
 }
@@ -459,6 +522,7 @@ hipError_t gemm(Elem t, bool a_trans, bool b_trans, const GemmArgs& g, hipStream
   // are multiples of the vector width, and the base is 16-byte aligned
   const int64_t a_cont = a_trans ? g.M : g.Kd, b_cont = b_trans ? g.Kd : g.N;
   const bool vec = aligned16(g.A) && aligned16(g.B) && g.lda % vw == 0 && g.ldb % vw == 0 &&
+                   g.lda < (int64_t(1) << 22) && g.ldb < (int64_t(1) << 22) &&
                    a_cont % vw == 0 && b_cont % vw == 0 &&
                    (g.splits <= 1 || g.k_per_split % vw == 0);
   dim3 grid((unsigned)((g.M + BM - 1) / BM), (unsigned)((g.N + BN - 1) / BN),
