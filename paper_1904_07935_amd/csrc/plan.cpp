@@ -86,8 +86,7 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
     need(D, K, V);
     need(V, K, D);
   }
-  const bool dense_rows = s.fmt == NMF_CSR && s.prec == NMF_FP32;
-  if (dense_rows) need(kDenseRowsMax, K, D);
+  if (s.fmt == NMF_CSR) need(kDenseRowsMax, K, D);  // the dense rows of A in P
   float* partial = c.take<float>(std::max<size_t>(part, 1));
   float* gpart = c.take<float>(gram_partial_floats((int)K, gram_max_chunks()));
   float* panel = c.take<float>(hals_panel_floats((int)K));
@@ -137,16 +136,13 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
     int32_t* slT = c.take<int32_t>((size_t)zT.items);
     int32_t* fixT = c.take<int32_t>((size_t)(3 * zT.fix));
     float* carryT = c.take<float>((size_t)(zT.seg * K));
-    float *a_top = nullptr, *c_top = nullptr;
-    int32_t* top_idx = nullptr;
-    if (s.prec == NMF_FP32) {
-      a_top = c.take<float>((size_t)kDenseRowsMax * D);
-      c_top = c.take<float>((size_t)kDenseRowsMax * K);
-      top_idx = c.take<int32_t>((size_t)kDenseRowsMax);
-    }
-    __bf16 *avb = nullptr, *tvb = nullptr, *xb = nullptr;
+    float* a_top = c.take<float>((size_t)kDenseRowsMax * D);
+    float* c_top = c.take<float>((size_t)kDenseRowsMax * K);
+    int32_t* top_idx = c.take<int32_t>((size_t)kDenseRowsMax);
+    __bf16 *avb = nullptr, *tvb = nullptr, *xb = nullptr, *atb = nullptr;
     float* P2 = nullptr;
     if (s.prec == NMF_BF16_PRODUCTS) {
+      atb = c.take<__bf16>((size_t)kDenseRowsMax * D);
       avb = c.take<__bf16>((size_t)std::max<int64_t>(nnz, 1));
       tvb = c.take<__bf16>((size_t)std::max<int64_t>(nnz, 1));
       xb = c.take<__bf16>((size_t)(std::max(V, D) * K));
@@ -166,6 +162,7 @@ void layout(const ShapeInfo& s, Carver& c, nmf_plan_s* p) {
       p->sp_At.fix = fixT;
       p->sp_At.carry = carryT;
       p->a_top = a_top;
+      p->a_top_bf = atb;
       p->c_top = c_top;
       p->top_idx = top_idx;
       p->a_val_bf = avb;
@@ -307,19 +304,21 @@ hipError_t product_P(nmf_plan_s* p, bool force_fp32, float* out) {
   const int K = p->K;
   const bool bf = p->prec == NMF_BF16_PRODUCTS && !force_fp32;
   if (p->fmt == NMF_CSR) {
+    hipError_t e;
     if (bf) {
-      hipError_t e = cast_bf16(p->Ht, p->X_bf, p->D * K, p->stream);
-      if (e != hipSuccess) return e;
-      return spmm(p->sp_A, Elem::BF16, p->X_bf, K, out, p->stream);
+      e = cast_bf16(p->Ht, p->X_bf, p->D * K, p->stream);
+      if (e == hipSuccess) e = spmm(p->sp_A, Elem::BF16, p->X_bf, K, out, p->stream);
+    } else {
+      e = spmm(p->prec == NMF_BF16_PRODUCTS ? p->sp_A_f32 : p->sp_A, Elem::F32, p->Ht, K, out,
+               p->stream);
     }
-    if (p->prec == NMF_BF16_PRODUCTS) return spmm(p->sp_A_f32, Elem::F32, p->Ht, K, out, p->stream);
-    hipError_t e = spmm(p->sp_A, Elem::F32, p->Ht, K, out, p->stream);
     if (e != hipSuccess || p->n_top == 0) return e;
-    // the dense rows: C_top [n_top, K] = A_top [n_top, D] H^T, then into their rows of P
+    // the dense rows: C_top [n_top, K] = A_top [n_top, D] H^T on the matrix
+    // cores (in the precision of the other products), then into their rows of P
     GemmArgs g{};
-    g.A = p->a_top;
+    g.A = bf ? (const void*)p->a_top_bf : (const void*)p->a_top;
     g.lda = p->D;
-    g.B = p->Ht;  // B(d,k) = Ht[d*K + k]
+    g.B = bf ? (const void*)p->X_bf : (const void*)p->Ht;  // B(d,k) = Ht[d*K + k]
     g.ldb = K;
     g.M = p->n_top;
     g.N = K;
@@ -329,7 +328,7 @@ hipError_t product_P(nmf_plan_s* p, bool force_fp32, float* out) {
     g.epi = EPI_STORE;
     g.splits = gemm_pick_splits(g.M, g.N, g.Kd, &g.k_per_split);
     g.partial = p->partial;
-    e = gemm(Elem::F32, false, false, g, p->stream);
+    e = gemm(bf ? Elem::BF16 : Elem::F32, false, false, g, p->stream);
     if (e != hipSuccess) return e;
     return scatter_rows(p->c_top, p->top_idx, p->n_top, K, out, p->stream);
   }
@@ -678,7 +677,7 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
     p->sp_At.val = p->t_val;
     std::vector<uint8_t> skip;
     const int drm = dense_rows_mode();
-    if (precision == NMF_FP32 && (drm == 1 || (drm < 0 && s.D * (int64_t)K >= kDenseRowsMinDK))) {
+    if (drm == 1 || (drm < 0 && s.D * (int64_t)K >= kDenseRowsMinDK)) {
       // the densest rows of A (longer than one work item and at least 1/16
       // dense; at most kDenseRowsMax, longest first) are multiplied as a dense
       // block on the matrix cores; the sparse product skips them.  Only when
@@ -708,6 +707,8 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
                                  hipMemcpyHostToDevice, st));
         INITCHECK(csr_dense_rows(A->rowptr, A->colidx, A->values, p->top_idx, p->n_top, s.D,
                                  p->a_top, st));
+        if (precision == NMF_BF16_PRODUCTS)
+          INITCHECK(cast_bf16(p->a_top, p->a_top_bf, (int64_t)p->n_top * s.D, st));
         INITCHECK(hipStreamSynchronize(st));  // cand is a host buffer
       }
     }

@@ -70,7 +70,8 @@ struct nmf_plan_s {
   __bf16* X_bf = nullptr;   // per-sweep BF16 cast of W or Ht
   plnmf::SpmmPlan sp_A{}, sp_At{};
   plnmf::SpmmPlan sp_A_f32{};  // FP32 values of A (objective of BF16 plans)
-  float* a_top = nullptr;       // [n_top, D] the densest rows of A, dense (FP32 CSR plans)
+  float* a_top = nullptr;       // [n_top, D] the densest rows of A, dense (CSR plans)
+  __bf16* a_top_bf = nullptr;   // the same in BF16 (CSR plans with BF16 products)
   float* c_top = nullptr;       // [n_top, K] their rows of P
   int32_t* top_idx = nullptr;   // [n_top] their row indices
   int n_top = 0;

@@ -21,8 +21,13 @@
 // The flat variant loads the item's row pointers, column indices and values
 // into registers at once (the item bounds are known), then walks the item's
 // nonzeros as one list, 16 gathers in flight per step, and writes out each row
-// as its end is passed.  Summation order within a row is the nonzero order,
-// as in the row-by-row kernel.
+// as its end is passed.  BF16 rows stay packed in registers until use, so a
+// batch holds 16 nonzeros at K up to 512 (FP32 at K > 256: 8); measured on
+// the 10^5 x 3*10^5 corpus at K = 400, the BF16 product of A^T W runs at half
+// the FP32 time that way, while deeper FP32 batches (16, at 3 waves/SIMD)
+// gain nothing -- the FP32 gathers are bound by the memory system there.
+// Summation order within a row is the nonzero order, as in the row-by-row
+// kernel.
 #include <algorithm>
 #include <vector>
 
@@ -148,24 +153,14 @@ __device__ __forceinline__ V wave_elem(const V (&arr)[N], int k) {
   return __builtin_bit_cast(V, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k & 63));
 }
 
-// Eight consecutive BF16 elements of a factor row (one 16-byte load) as floats.
-__device__ __forceinline__ void ld_x8(const __bf16* row, int c, int K, floatx4& lo, floatx4& hi) {
-  if (c < K) {
-    const bf16x8 b = *(const bf16x8*)(row + c);
-    lo = floatx4{(float)b[0], (float)b[1], (float)b[2], (float)b[3]};
-    hi = floatx4{(float)b[4], (float)b[5], (float)b[6], (float)b[7]};
-  } else {
-    lo = hi = floatx4{0, 0, 0, 0};
-  }
-}
-
 // EPL: factor elements per lane and load -- 4 (FP32 float4, or BF16 8-byte
 // loads), or 8 (BF16 16-byte loads; K % 8 == 0, rows 16-byte aligned).
-template <int VPL, typename TV, typename TX, bool VEC, int EPL = 4>
+template <int VPL, typename TV, typename TX, bool VEC, int EPL = 4, int UNR_ = 0>
 __global__ __launch_bounds__(256) void spmm_flat(SpmmKArgs a) {
-  static_assert(EPL == 4 || (EPL == 8 && VEC && sizeof(TX) == 2), "16-byte BF16 loads only");
+  static_assert(EPL == 4 || (EPL == 8 && VEC && sizeof(TX) == 2 && VPL == 1),
+                "16-byte BF16 loads only");
   constexpr int NQ = EPL / 4;  // float4 accumulators per load
-  constexpr int UNR = VPL * NQ == 1 ? 16 : 8;
+  constexpr int UNR = UNR_ ? UNR_ : ((EPL == 8 || VPL == 1) ? 16 : 8);  // gathers per batch
   constexpr int MZ = kFlatMaxNnz / 64;
   constexpr int MR = (kMaxRowsPerItem + 1 + 63) / 64;
   const int lane = threadIdx.x & 63;
@@ -220,34 +215,53 @@ __global__ __launch_bounds__(256) void spmm_flat(SpmmKArgs a) {
     r++;
     rend = r < nr ? row_end(r) : nz;
   };
-  for (int jb = 0; jb < nz; jb += UNR) {
-    floatx4 x[UNR][VPL * NQ];
+  if constexpr (EPL == 8) {
+    // BF16 rows kept packed until use (4 VGPRs per nonzero), so twice as
+    // many gathers are in flight per wave as with unpacked floats
+    for (int jb = 0; jb < nz; jb += UNR) {
+      bf16x8 xb[UNR];
 #pragma unroll
-    for (int u = 0; u < UNR; u++) {
-      const int j = jb + u;
-      const int64_t col = j < nz ? wave_elem(pc, j) : 0;
+      for (int u = 0; u < UNR; u++) {
+        const int j = jb + u;
+        const int64_t col = j < nz ? wave_elem(pc, j) : 0;
+        const int cb = 8 * lane;
+        xb[u] = (j < nz && cb < K) ? *(const bf16x8*)((const __bf16*)X + col * a.ldx + cb)
+                                   : bf16x8{};
+      }
 #pragma unroll
-      for (int v = 0; v < VPL; v++) {
-        const int cb = EPL * (lane + 64 * v);
-        if constexpr (EPL == 8) {
-          if (j < nz) {
-            ld_x8((const __bf16*)(X + col * a.ldx), cb, K, x[u][v * NQ], x[u][v * NQ + 1]);
-          } else {
-            x[u][v * NQ] = x[u][v * NQ + 1] = floatx4{0, 0, 0, 0};
-          }
-        } else {
-          x[u][v] = j < nz ? ld_x4<TX, VEC>(X + col * a.ldx, cb, K) : floatx4{0, 0, 0, 0};
+      for (int u = 0; u < UNR; u++) {
+        const int j = jb + u;
+        if (j < nz) {
+          while (j >= rend && r < nr) flush();
+          const float vv = wave_elem(pv, j);
+          const bf16x8 b = xb[u];
+          acc[0] += vv * floatx4{(float)b[0], (float)b[1], (float)b[2], (float)b[3]};
+          acc[1] += vv * floatx4{(float)b[4], (float)b[5], (float)b[6], (float)b[7]};
         }
       }
     }
+  } else {
+    for (int jb = 0; jb < nz; jb += UNR) {
+      floatx4 x[UNR][VPL];
 #pragma unroll
-    for (int u = 0; u < UNR; u++) {
-      const int j = jb + u;
-      if (j < nz) {
-        while (j >= rend && r < nr) flush();  // rows that end here, empty ones included
-        const float vv = wave_elem(pv, j);
+      for (int u = 0; u < UNR; u++) {
+        const int j = jb + u;
+        const int64_t col = j < nz ? wave_elem(pc, j) : 0;
 #pragma unroll
-        for (int v = 0; v < VPL * NQ; v++) acc[v] += vv * x[u][v];
+        for (int v = 0; v < VPL; v++) {
+          const int cb = EPL * (lane + 64 * v);
+          x[u][v] = j < nz ? ld_x4<TX, VEC>(X + col * a.ldx, cb, K) : floatx4{0, 0, 0, 0};
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; u++) {
+        const int j = jb + u;
+        if (j < nz) {
+          while (j >= rend && r < nr) flush();  // rows that end here, empty ones included
+          const float vv = wave_elem(pv, j);
+#pragma unroll
+          for (int v = 0; v < VPL; v++) acc[v] += vv * x[u][v];
+        }
       }
     }
   }

@@ -232,3 +232,34 @@ def test_c4_sampled_h_half_and_properties(cuda):
     _, r2 = plan.objective()
     assert r2 <= r1 * (1 + 1e-6)
     plan.close()
+
+
+@pytest.mark.parametrize("K", [16, 200])
+def test_bf16_dense_rows_in_p_product(cuda, monkeypatch, K):
+    """BF16 products with the densest rows of A taken out of the sparse P
+    product and multiplied on the matrix cores in BF16 (NMF_DENSE_ROWS=1 forces
+    it at this size): P equals the product of the BF16-rounded inputs up to
+    FP32 accumulation, element by element; the objective, whose FP32 P takes
+    the same rows through the FP32 matrix-core product, equals the oracle's
+    objective of the plan's own factors; eight sweeps stay within the BF16 bar."""
+    import scipy.sparse as sp
+    monkeypatch.setenv("NMF_DENSE_ROWS", "1")
+    c = small_bow()
+    lens = np.diff(c.A.rowptr)
+    assert np.sum((lens > 128) & (16 * lens >= c.A.cols)) >= 3  # several rows qualify
+    W0, H0 = sparse_init(c, K)
+    Ao = oracle_A(c.A)
+    p16 = gpu_plan(c.A, W0, H0, cuda, precision="bf16")
+    p16.half("W")
+    Ab = sp.csr_matrix((bf16_round(c.A.val), c.A.col, c.A.rowptr), shape=(c.A.rows, c.A.cols))
+    Pb = np.asarray(Ab @ bf16_round(H0.astype(np.float32).astype(np.float64)).T)
+    assert elem_rel_max(_np(p16.intermediates()["P"]), Pb) <= 1e-4
+    _, rel = p16.objective()
+    want = hals.objective(Ao, _np(p16.W), _np(p16.Ht).T)[1]
+    assert abs(rel - want) / want <= 1e-5
+    p16.close()
+    p16 = gpu_plan(c.A, W0, H0, cuda, precision="bf16")
+    r16 = np.array(p16.sweep(8, objective=True))
+    rel_or, _ = oracle_run(c.A, W0, H0, 8)
+    assert np.max(np.abs(r16 - rel_or) / np.array(rel_or)) <= BF16_REL_BOUND
+    p16.close()
