@@ -484,7 +484,7 @@ int gemm_pick_splits(int64_t M, int64_t N, int64_t Kd, int64_t* k_per_split) {
   constexpr double kBytesPerSec = 4.0e12;
   int best = 1;
   double best_t = 0.0;
-  for (int s = 1; s <= 64; s++) {
+  for (int s = 1; s <= 256; s++) {
     if (s > 1 && Kd / s < 256) break;
     int64_t kps = (Kd + s - 1) / s;
     kps = (kps + 31) / 32 * 32;
