@@ -45,8 +45,21 @@ __device__ __forceinline__ bf16x8 ld8h(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
+// erf(x) by Abramowitz and Stegun's rational approximation 7.1.26
+// (|error| <= 1.5e-7), branch-free with the hardware exponential: the GELU
+// epilogue runs on every hidden activation, and its outputs are rounded to
+// BF16 (2^-9) right after.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __frcp_rn(1.0f + 0.3275911f * ax);
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f +
+                                                                        t * 1.061405429f))));
+  const float y = 1.0f - poly * __expf(-ax * ax);
+  return copysignf(y, x);
+}
 __device__ __forceinline__ float gelu_f(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+  return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
 }
 __device__ __forceinline__ float gelu_grad_f(float z) {
   float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
@@ -359,14 +372,17 @@ struct Mfma<__bf16> {
 // computing step k + 1, so each load has two compute steps to arrive.  The
 // loop body is a pair of steps (an odd count gets one step of zeros).
 //
-// Two-level accumulation: the matrix cores accumulate each pair of K-steps
-// (32 terms in FP32, 64 in BF16) into a fresh accumulator, which is then added
-// to the running total.  A single accumulator chain over a contraction of n
-// terms carries a rounding error that grows like sqrt(n) units of FP32
-// rounding; with chunks of c terms the chain is n / c long, which cuts the
-// error of the 800 - 10^4 term products several times.  A chunk per loop
-// iteration keeps the fresh accumulator local to the body, so it stays in
-// the matrix-core registers instead of moving through the VALU every step.
+// FP32: two-level accumulation.  The matrix cores accumulate each pair of
+// K-steps (32 terms) into a fresh accumulator, which is then added to the
+// running total.  A single accumulator chain over a contraction of n terms
+// carries a rounding error that grows like sqrt(n) units of FP32 rounding;
+// with chunks of c terms the chain is n / c long, which cuts the error of the
+// 800 - 10^4 term products several times.  A chunk per loop iteration keeps
+// the fresh accumulator local to the body, so it stays in the matrix-core
+// registers instead of moving through the VALU every step.
+// BF16: one chain.  The inputs' rounding (2^-9 relative) dwarfs the FP32
+// chain's, and at BF16 rates the chunk additions would cost as much VALU time
+// as the products take on the matrix cores.
 template <typename T, typename St, typename TA, typename TB>
 __device__ __forceinline__ void pipeline(TA As, TB Bs, const T* __restrict__ A,
                                          const T* __restrict__ B, int64_t lda, int64_t ldb,
@@ -374,21 +390,14 @@ __device__ __forceinline__ void pipeline(TA As, TB Bs, const T* __restrict__ A,
                                          int64_t kb, int64_t ke, int nk, int tid,
                                          floatx16 (&tot)[2][2], int wm, int wn, int lane) {
   constexpr int BK = Mfma<T>::BK;
+  constexpr bool kChunked = std::is_same<T, float>::value;
   if (nk <= 0) return;
   St s0, s1;
   s0.load(A, B, lda, ldb, M, N, m0, n0, kb, ke, Kd, tid);
   s1.load(A, B, lda, ldb, M, N, m0, n0, kb + BK, ke, Kd, tid);
   s0.store(As[0], Bs[0], tid);
   __syncthreads();
-#pragma unroll 1
-  for (int kt = 0; kt < nk; kt += 2) {
-    floatx16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-      for (int j = 0; j < 2; j++)
-#pragma unroll
-        for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+  auto pair = [&](int kt, floatx16(&acc)[2][2]) {
     s0.load(A, B, lda, ldb, M, N, m0, n0, kb + (int64_t)(kt + 2) * BK, ke, Kd, tid);
     Mfma<T>::step(As[0], Bs[0], acc, wm, wn, lane);
     s1.store(As[1], Bs[1], tid);
@@ -397,10 +406,26 @@ __device__ __forceinline__ void pipeline(TA As, TB Bs, const T* __restrict__ A,
     Mfma<T>::step(As[1], Bs[1], acc, wm, wn, lane);
     s0.store(As[0], Bs[0], tid);
     __syncthreads();
+  };
+  if constexpr (kChunked) {
+#pragma unroll 1
+    for (int kt = 0; kt < nk; kt += 2) {
+      floatx16 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+      for (int i = 0; i < 2; i++)
 #pragma unroll
-      for (int j = 0; j < 2; j++) tot[i][j] += acc[i][j];
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+          for (int e = 0; e < 16; e++) acc[i][j][e] = 0.0f;
+      pair(kt, acc);
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) tot[i][j] += acc[i][j];
+    }
+  } else {
+#pragma unroll 1
+    for (int kt = 0; kt < nk; kt += 2) pair(kt, tot);
   }
 }
 
