@@ -72,17 +72,19 @@ __device__ __forceinline__ float softplus_f(float z) {
 
 // Epilogue over one wave's 2 x 2 blocks.  `acc[i][j]` is the 32x32 block at
 // rows r0 + 32 i, cols c0 + 32 j.  Every field is passed by value so nothing
-// here takes the address of the kernel argument block.
-__device__ __forceinline__ void epilogue(int epi, int64_t M, int64_t N, float* __restrict__ out,
-                                         int64_t ldo, bool split, const float* __restrict__ bias,
-                                         const float* Dm, int64_t ldd,
-                                         void* __restrict__ C2, float* C,
-                                         int64_t ldc, double* __restrict__ red_out,
-                                         floatx16 (&acc)[2][2], int64_t r0, int64_t c0,
-                                         double* red_smem, bool mirror, float mu_delta,
-                                         int64_t red_slot) {
+// here takes the address of the kernel argument block.  The epilogue kind and
+// whether the wave's 64 x 64 block lies wholly inside C are template
+// parameters: each instantiation is one straight run of 64 element updates,
+// with no per-element dispatch on the kind and, inside C, no bounds checks.
+template <int EPI, bool FULL>
+__device__ __forceinline__ void epi_block(int64_t M, int64_t N, float* __restrict__ out,
+                                          int64_t ldo, bool split, const float* __restrict__ bias,
+                                          const float* Dm, int64_t ldd, void* __restrict__ C2,
+                                          float* C, int64_t ldc, floatx16 (&acc)[2][2],
+                                          int64_t r0, int64_t c0, bool mirror, float mu_delta,
+                                          double& ss) {
   const int lane = threadIdx.x & 63;
-  double ss = 0.0;
+  const float* bs = (EPI != EPI_STORE || !split) ? bias : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
@@ -93,33 +95,71 @@ __device__ __forceinline__ void epilogue(int epi, int64_t M, int64_t N, float* _
         for (int ii = 0; ii < 4; ii++) {
           const int64_t m = r0 + 32 * i + 8 * jj + 4 * (lane >> 5) + ii;
           const int64_t n = c0 + 32 * j + (lane & 31);
-          if (m >= M || n >= N) continue;
+          if (!FULL && (m >= M || n >= N)) continue;
           float v = acc[i][j][jj * 4 + ii];
-          if (epi == EPI_STORE) {
-            if (!split && bias) v += bias[n];
+          if constexpr (EPI == EPI_STORE) {
+            if (bs) v += bs[n];
             out[m * ldo + n] = v;
             if (mirror) out[n * ldo + m] = v;  // symmetric product, tile above the diagonal
-          } else if (epi == EPI_RESID_SQ) {
+          } else if constexpr (EPI == EPI_RESID_SQ) {
             const float e = Dm[m * ldd + n] - v;
             ss += (double)e * (double)e;
-          } else if (epi == EPI_BIAS_GELU) {
-            const float z = v + bias[n];
+          } else if constexpr (EPI == EPI_BIAS_GELU) {
+            const float z = v + bs[n];
             if (C) C[m * ldc + n] = z;
             ((__bf16*)C2)[m * ldc + n] = (__bf16)gelu_f(z);
-          } else if (epi == EPI_BIAS_SOFTPLUS) {
-            const float z = v + bias[n];
+          } else if constexpr (EPI == EPI_BIAS_SOFTPLUS) {
+            const float z = v + bs[n];
             if (C) C[m * ldc + n] = z;
             ((float*)C2)[m * ldc + n] = softplus_f(z);
-          } else if (epi == EPI_GELU_GRAD) {
+          } else if constexpr (EPI == EPI_GELU_GRAD) {
             const float d = v * gelu_grad_f(Dm[m * ldd + n]);
             if (C) C[m * ldc + n] = d;
             ((__bf16*)C2)[m * ldc + n] = (__bf16)d;
-          } else if (epi == EPI_MU) {
+          } else if constexpr (EPI == EPI_MU) {
             const float num = Dm[m * ldd + n], x = ((const float*)C2)[m * ldc + n];
             C[m * ldc + n] = x * num / (v + mu_delta);
           }
         }
+}
+
+template <int EPI>
+__device__ __forceinline__ void epi_kind(int64_t M, int64_t N, float* __restrict__ out,
+                                         int64_t ldo, bool split, const float* __restrict__ bias,
+                                         const float* Dm, int64_t ldd, void* __restrict__ C2,
+                                         float* C, int64_t ldc, floatx16 (&acc)[2][2], int64_t r0,
+                                         int64_t c0, bool mirror, float mu_delta, double& ss) {
+  if (r0 + 64 <= M && c0 + 64 <= N)
+    epi_block<EPI, true>(M, N, out, ldo, split, bias, Dm, ldd, C2, C, ldc, acc, r0, c0, mirror,
+                         mu_delta, ss);
+  else
+    epi_block<EPI, false>(M, N, out, ldo, split, bias, Dm, ldd, C2, C, ldc, acc, r0, c0, mirror,
+                          mu_delta, ss);
+}
+
+__device__ __forceinline__ void epilogue(int epi, int64_t M, int64_t N, float* __restrict__ out,
+                                         int64_t ldo, bool split, const float* __restrict__ bias,
+                                         const float* Dm, int64_t ldd,
+                                         void* __restrict__ C2, float* C,
+                                         int64_t ldc, double* __restrict__ red_out,
+                                         floatx16 (&acc)[2][2], int64_t r0, int64_t c0,
+                                         double* red_smem, bool mirror, float mu_delta,
+                                         int64_t red_slot) {
+  double ss = 0.0;
+#define PLNMF_EPI(K)                                                                        \
+  epi_kind<K>(M, N, out, ldo, split, bias, Dm, ldd, C2, C, ldc, acc, r0, c0, mirror, mu_delta, \
+              ss)
+  switch (epi) {
+    case EPI_STORE: PLNMF_EPI(EPI_STORE); break;
+    case EPI_RESID_SQ: PLNMF_EPI(EPI_RESID_SQ); break;
+    case EPI_BIAS_GELU: PLNMF_EPI(EPI_BIAS_GELU); break;
+    case EPI_BIAS_SOFTPLUS: PLNMF_EPI(EPI_BIAS_SOFTPLUS); break;
+    case EPI_GELU_GRAD: PLNMF_EPI(EPI_GELU_GRAD); break;
+    case EPI_MU: PLNMF_EPI(EPI_MU); break;
+  }
+#undef PLNMF_EPI
   if (epi == EPI_RESID_SQ) {
+    const int lane = threadIdx.x & 63;
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
     const int w = threadIdx.x >> 6;
     if (lane == 0) red_smem[w] = ss;
