@@ -13,6 +13,9 @@ namespace plnmf {
 int mlp_forward_impl(const void* params, int K, int H, const float* X, float* Y, int64_t N,
                      void* ws, size_t bytes, hipStream_t s);
 size_t mlp_ws_bytes(int K, int H, int64_t B);
+int mlp_warm_start(const void* params, int K, int H, const float* R, int64_t N, float eps,
+                   float* out, float* xn, float* norms, float* y, void* ws, size_t bytes,
+                   hipStream_t s);
 }  // namespace plnmf
 
 namespace {
@@ -223,10 +226,9 @@ int plnmf::foldin_run(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int in
   if (init_mode == NMF_FOLDIN_WTA) {
     FCHECK(clip_min(f.R, Dn * K, p->eps, Ht_new, s));
   } else if (init_mode == NMF_FOLDIN_MLP) {
-    FCHECK(row_normalize(f.R, Dn, K, f.xn, f.norms, s));
-    rc = mlp_forward_impl(mlp_params, K, mlp_hidden, f.xn, f.y, Dn, f.mlp_ws, f.mlp_ws_bytes, s);
+    rc = mlp_warm_start(mlp_params, K, mlp_hidden, f.R, Dn, p->eps, Ht_new, f.xn, f.norms, f.y,
+                        f.mlp_ws, f.mlp_ws_bytes, s);
     if (rc) return rc;
-    FCHECK(rescale_clip_rows(f.y, f.norms, Dn, K, p->eps, Ht_new, s));
   }
 
   HalsArgs a{};

@@ -45,29 +45,10 @@ __device__ __forceinline__ bf16x8 ld8h(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
-// erf(x) by Abramowitz and Stegun's rational approximation 7.1.26
-// (|error| <= 1.5e-7), branch-free with the hardware exponential: the GELU
-// epilogue runs on every hidden activation, and its outputs are rounded to
-// BF16 (2^-9) right after.
-__device__ __forceinline__ float erf_as(float x) {
-  const float ax = fabsf(x);
-  const float t = __frcp_rn(1.0f + 0.3275911f * ax);
-  const float poly =
-      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f +
-                                                                        t * 1.061405429f))));
-  const float y = 1.0f - poly * __expf(-ax * ax);
-  return copysignf(y, x);
-}
-__device__ __forceinline__ float gelu_f(float z) {
-  return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
-}
 __device__ __forceinline__ float gelu_grad_f(float z) {
   float cdf = 0.5f * (1.0f + erff(z * 0.70710678118654752f));
   float pdf = expf(-0.5f * z * z) * 0.39894228040143268f;
   return cdf + z * pdf;
-}
-__device__ __forceinline__ float softplus_f(float z) {
-  return z > 20.0f ? z : log1pf(expf(z));
 }
 
 // Epilogue over one wave's 2 x 2 blocks.  `acc[i][j]` is the 32x32 block at

@@ -7,6 +7,29 @@
 
 namespace plnmf {
 
+// Activations of the warm-start network, shared by the GEMM epilogues and the
+// fused inference kernel.
+// erf(x) by Abramowitz and Stegun's rational approximation 7.1.26
+// (|error| <= 1.5e-7), branch-free with the hardware exponential: the GELU
+// epilogue runs on every hidden activation, and its outputs are rounded to
+// BF16 (2^-9) right after.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __frcp_rn(1.0f + 0.3275911f * ax);
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f +
+                                                                        t * 1.061405429f))));
+  const float y = 1.0f - poly * __expf(-ax * ax);
+  return copysignf(y, x);
+}
+__device__ __forceinline__ float gelu_f(float z) {
+  return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
+}
+__device__ __forceinline__ float softplus_f(float z) {
+  return z > 20.0f ? z : log1pf(expf(z));
+}
+
+
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -223,6 +246,13 @@ hipError_t gather_rows(const float* x, const int32_t* idx, int64_t n, int64_t co
                        hipStream_t s);
 hipError_t row_normalize(const float* x, int64_t rows, int64_t cols, float* xn, float* norms,
                          hipStream_t s);
+// The network's fused inference for fold-in: out = max(eps, ||r|| softplus(W2
+// GELU(W1 r/||r|| + b1) + b2)) per row r of R [N, K]; BF16 weights.  Only for
+// K % 8 == 0, K <= 208, hidden % 32 == 0 (mlp_infer_fused_ok).
+bool mlp_infer_fused_ok(int K, int H);
+hipError_t mlp_infer_fused(const float* R, int64_t N, int K, int H, const __bf16* W1b,
+                           const float* b1, const __bf16* W2b, const float* b2, float eps,
+                           float* out, hipStream_t s);
 hipError_t rescale_clip_rows(const float* y, const float* norms, int64_t rows, int64_t cols,
                              float eps, float* out, hipStream_t s);
 hipError_t clip_min(const float* x, int64_t n, float eps, float* out, hipStream_t s);

@@ -126,6 +126,183 @@ __global__ void clip_kernel(const float* __restrict__ x, int64_t n, float eps, f
     out[i] = fmaxf(eps, x[i]);
 }
 
+
+// Fused inference of the network for fold-in: for each row r of R = A_new^T W
+//   x = r / ||r|| (BF16),  g = GELU(W1 x + b1) (BF16),
+//   h0 = max(eps, ||r|| softplus(W2 g + b2)),
+// the arithmetic of the two-GEMM path (BF16 operands, FP32 accumulation) in
+// one pass over R and one write of h0, with nothing of the hidden layer
+// leaving the CU.  A workgroup is eight waves of 32 rows.  A wave holds its
+// rows' x in registers in the A-operand layout of the 32x32x16 BF16 matrix-core
+// product (lane (m, h) holds row m's elements 16 s + 8 h .. + 7 in xf[s]) and
+// walks the hidden units in chunks of 32: the chunk's 32-wide block of W1 x
+// on the matrix cores, bias + GELU in its output layout, a transpose of the
+// 32 x 32 activations through the wave's own LDS rows, then their product
+// with the chunk's columns of W2 into the output accumulators.  The chunk's
+// weights are staged in LDS for all eight waves, the next chunk's already in
+// flight in registers.  Needs K % 8 == 0, K <= 208 and hidden % 32 == 0.
+constexpr int kInfWaves = 8, kInfRows = 32 * kInfWaves, kHC = 32;
+
+struct MlpInferArgs {
+  const float* R;
+  int64_t N;
+  int K, H;
+  const __bf16* W1b;  // [H, K]
+  const float* b1;    // [H]
+  const __bf16* W2b;  // [K, H]
+  const float* b2;    // [K]
+  float eps;
+  float* out;         // [N, K]
+};
+
+__host__ __device__ constexpr int inf_kp1(int NKB) { return 16 * NKB + 8; }  // W1 row pitch
+constexpr int kInfHP = kHC + 8;                                              // W2 / G row pitch
+__host__ __device__ constexpr size_t inf_smem_bytes(int NKB) {
+  return 2 * ((size_t)kHC * inf_kp1(NKB) + (size_t)32 * ((NKB + 1) / 2) * kInfHP +
+              (size_t)kInfWaves * 32 * kInfHP) +
+         4 * (size_t)kInfWaves * 32;
+}
+
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NKB>
+__global__ __launch_bounds__(512) void mlp_infer_kernel(MlpInferArgs a) {
+  constexpr int NB2 = (NKB + 1) / 2;  // 32-column output blocks: 32 NB2 >= 16 NKB >= K
+  constexpr int KP1 = inf_kp1(NKB), HP = kInfHP;
+  constexpr int P1 = kHC * 2 * NKB, P2 = 32 * NB2 * (kHC / 8);  // 16-byte pieces per chunk
+  constexpr int L1 = (P1 + 511) / 512, L2 = (P2 + 511) / 512;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __bf16* w1s = (__bf16*)smem;                       // [kHC][KP1]
+  __bf16* w2s = w1s + kHC * KP1;                     // [32 NB2][HP]
+  __bf16* gs = w2s + 32 * NB2 * HP;                  // [waves][32][HP]
+  float* nrs = (float*)(gs + kInfWaves * 32 * HP);   // [waves][32]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int m = lane & 31, h = lane >> 5;
+  const int K = a.K, H = a.H;
+  const int64_t r0 = (int64_t)blockIdx.x * kInfRows + 32 * w;
+  const int64_t row = r0 + m;
+  const bf16x8 zero8 = {};
+
+  // this lane's pieces of its row, the row's norm, and x in BF16
+  bf16x8 xf[NKB];
+  {
+    floatx4 v[NKB][2];
+    float ss = 0.0f;
+#pragma unroll
+    for (int s = 0; s < NKB; s++)
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        const int k = 16 * s + 8 * h + 4 * q;
+        v[s][q] = (row < a.N && k < K) ? *(const floatx4*)(a.R + row * K + k) : floatx4{0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 4; e++) ss += v[s][q][e] * v[s][q][e];
+      }
+    ss += __shfl_xor(ss, 32);
+    const float nrm = sqrtf(ss);
+#pragma unroll
+    for (int s = 0; s < NKB; s++)
+#pragma unroll
+      for (int e = 0; e < 8; e++)
+        xf[s][e] = (__bf16)(nrm > 0.0f ? v[s][e >> 2][e & 3] / nrm : 0.0f);
+    if (h == 0) nrs[32 * w + m] = nrm;
+  }
+
+  bf16x8 pre1[L1], pre2[L2];
+  auto fetch = [&](int c) {
+#pragma unroll
+    for (int u = 0; u < L1; u++) {
+      const int i = tid + 512 * u;
+      const int jl = i / (2 * NKB), k = 8 * (i % (2 * NKB));
+      pre1[u] = (i < P1 && k < K) ? *(const bf16x8*)(a.W1b + (int64_t)(c * kHC + jl) * K + k)
+                                  : zero8;
+    }
+#pragma unroll
+    for (int u = 0; u < L2; u++) {
+      const int i = tid + 512 * u;
+      const int kr = i / (kHC / 8), hq = i % (kHC / 8);
+      pre2[u] = (i < P2 && kr < K) ? *(const bf16x8*)(a.W2b + (int64_t)kr * H + c * kHC + 8 * hq)
+                                   : zero8;
+    }
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int u = 0; u < L1; u++) {
+      const int i = tid + 512 * u;
+      if (i < P1) *(bf16x8*)(w1s + (i / (2 * NKB)) * KP1 + 8 * (i % (2 * NKB))) = pre1[u];
+    }
+#pragma unroll
+    for (int u = 0; u < L2; u++) {
+      const int i = tid + 512 * u;
+      if (i < P2) *(bf16x8*)(w2s + (i / (kHC / 8)) * HP + 8 * (i % (kHC / 8))) = pre2[u];
+    }
+  };
+
+  floatx16 acc2[NB2];
+#pragma unroll
+  for (int o = 0; o < NB2; o++)
+#pragma unroll
+    for (int e = 0; e < 16; e++) acc2[o][e] = 0.0f;
+  __bf16* gw = gs + 32 * w * HP;  // this wave's activation rows
+  const int nch = H / kHC;
+  fetch(0);
+#pragma unroll 1
+  for (int c = 0; c < nch; c++) {
+    put();
+    __syncthreads();
+    if (c + 1 < nch) fetch(c + 1);
+    // W1 x for the chunk's 32 hidden units
+    floatx16 acc1;
+#pragma unroll
+    for (int e = 0; e < 16; e++) acc1[e] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < NKB; s++) {
+      const bf16x8 wb = *(const bf16x8*)(w1s + m * KP1 + 16 * s + 8 * h);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wb, acc1, 0, 0, 0);
+    }
+    // bias + GELU; lane holds rows 8 jj + 4 h + i of hidden unit m
+    {
+      const float bb = a.b1[c * kHC + m];
+#pragma unroll
+      for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          gw[(8 * jj + 4 * h + i) * HP + m] = (__bf16)gelu_f(acc1[4 * jj + i] + bb);
+    }
+    wave_lds_order();
+    // activations (A operand: row m, hidden 16 t + 8 h ..) times the chunk's W2 columns
+#pragma unroll
+    for (int t = 0; t < kHC / 16; t++) {
+      const bf16x8 gf = *(const bf16x8*)(gw + m * HP + 16 * t + 8 * h);
+#pragma unroll
+      for (int o = 0; o < NB2; o++) {
+        const bf16x8 wf = *(const bf16x8*)(w2s + (32 * o + m) * HP + 16 * t + 8 * h);
+        acc2[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(gf, wf, acc2[o], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // the chunk's weights are no longer read
+  }
+  // bias + softplus, rescaled by the row's norm and clipped at eps
+#pragma unroll
+  for (int o = 0; o < NB2; o++) {
+    const int kc = 32 * o + m;
+    if (kc >= K) continue;
+    const float bb = a.b2[kc];
+#pragma unroll
+    for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int rr = 8 * jj + 4 * h + i;
+        if (r0 + rr >= a.N) continue;
+        const float y = softplus_f(acc2[o][4 * jj + i] + bb);
+        a.out[(r0 + rr) * K + kc] = fmaxf(a.eps, nrs[32 * w + rr] * y);
+      }
+  }
+}
+
 int grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 4096) b = 4096;
@@ -181,6 +358,39 @@ hipError_t row_normalize(const float* x, int64_t rows, int64_t cols, float* xn, 
 hipError_t rescale_clip_rows(const float* y, const float* norms, int64_t rows, int64_t cols,
                              float eps, float* out, hipStream_t s) {
   rescale_kernel<<<grid_for(rows * cols), 256, 0, s>>>(y, norms, rows, cols, eps, out);
+  return hipGetLastError();
+}
+
+
+// K <= 208: at most 13 steps of x in registers (at 14 the kernel would spill)
+bool mlp_infer_fused_ok(int K, int H) {
+  return K >= 1 && K <= 208 && K % 8 == 0 && H >= kHC && H % kHC == 0;
+}
+
+hipError_t mlp_infer_fused(const float* R, int64_t N, int K, int H, const __bf16* W1b,
+                           const float* b1, const __bf16* W2b, const float* b2, float eps,
+                           float* out, hipStream_t s) {
+  if (!mlp_infer_fused_ok(K, H)) return hipErrorInvalidValue;
+  if (N <= 0) return hipSuccess;
+  MlpInferArgs a{R, N, K, H, W1b, b1, W2b, b2, eps, out};
+  const unsigned blocks = (unsigned)((N + kInfRows - 1) / kInfRows);
+  const int nkb = (K + 15) / 16;  // 16-wide steps over the rank
+#define PLNMF_INF(NKB)                                                                        \
+  case NKB: {                                                                                 \
+    const size_t bytes = inf_smem_bytes(NKB);                                                 \
+    hipError_t e = hipFuncSetAttribute((const void*)mlp_infer_kernel<NKB>,                    \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes); \
+    if (e != hipSuccess) return e;                                                            \
+    mlp_infer_kernel<NKB><<<blocks, 512, bytes, s>>>(a);                                      \
+    break;                                                                                    \
+  }
+  switch (nkb) {
+    PLNMF_INF(1) PLNMF_INF(2) PLNMF_INF(3) PLNMF_INF(4) PLNMF_INF(5) PLNMF_INF(6)
+    PLNMF_INF(7) PLNMF_INF(8) PLNMF_INF(9) PLNMF_INF(10) PLNMF_INF(11) PLNMF_INF(12)
+    PLNMF_INF(13)
+    default: return hipErrorInvalidValue;
+  }
+#undef PLNMF_INF
   return hipGetLastError();
 }
 

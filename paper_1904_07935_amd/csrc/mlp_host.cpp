@@ -314,6 +314,25 @@ int mlp_forward_impl(const void* params, int K, int H, const float* X, float* Y,
   return NMF_OK;
 }
 size_t mlp_ws_bytes(int K, int H, int64_t B) { return ws_infer_layout(nullptr, K, H, B).off; }
+
+// The warm start of fold-in: Ht_new = max(eps, ||r|| mlp(r / ||r||)) per row r of
+// R.  One fused kernel where the shape allows it, else normalisation, the two
+// GEMMs and the rescaling as separate launches (xn, norms, y: [N, K], [N],
+// [N, K] scratch for that route).
+int mlp_warm_start(const void* params, int K, int H, const float* R, int64_t N, float eps,
+                   float* out, float* xn, float* norms, float* y, void* ws, size_t bytes,
+                   hipStream_t s) {
+  if (mlp_infer_fused_ok(K, H)) {
+    const Params p = view((void*)params, K, H);
+    MLPCHECK(mlp_infer_fused(R, N, K, H, p.W1b, p.b1, p.W2b, p.b2, eps, out, s));
+    return NMF_OK;
+  }
+  MLPCHECK(row_normalize(R, N, K, xn, norms, s));
+  int rc = mlp_forward_impl(params, K, H, xn, y, N, ws, bytes, s);
+  if (rc) return rc;
+  MLPCHECK(rescale_clip_rows(y, norms, N, K, eps, out, s));
+  return NMF_OK;
+}
 }  // namespace plnmf
 
 extern "C" {

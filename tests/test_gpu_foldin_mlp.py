@@ -134,6 +134,43 @@ def test_mlp_forward_and_warm_start_match_oracle(cuda):
     plan.close()
 
 
+@pytest.mark.parametrize("K,Hd,Dn", [(200, 512, 1000), (40, 96, 300), (8, 32, 257)])
+def test_fused_warm_start_matches_oracle_and_two_gemm_route(cuda, K, Hd, Dn):
+    """Fold-in's warm start runs as one fused kernel (x in registers, the hidden
+    layer through LDS, softplus, rescaling and the clip in the output
+    epilogue).  Against the FP64 oracle at the same BF16-rounded weights, and
+    element by element against the network's two-GEMM inference
+    (nmf_mlp_predict) on the same rows: the configured size, other hidden
+    widths (3 and 1 chunks of 32), row counts that leave the last 256-row
+    workgroup partly empty, and K = 8 (one 16-wide step, half of it padding)."""
+    import torch
+
+    from paper_1904_07935_amd.api import Matrix, Mlp
+    rng = np.random.default_rng(K + Hd)
+    p = _net(rng, K, Hd)
+    net = Mlp(K, Hd, device=cuda, seed=None)
+    net.set_masters(p)
+    c, W, new, plan = _fold_setup(cuda, K=K, Dn=Dn, sweeps=3)
+    M = Matrix.from_csr(new, cuda)
+    Ht = torch.zeros(new.rows, K, device=cuda)
+    plan.foldin(M, Ht, init="mlp", mlp=net, n_sweeps=0, trace=False)
+    got = _np(Ht)
+    assert np.all(np.isfinite(got)) and got.min() >= EPS * (1 - 1e-6)
+    Anew = rows_csr_to_oracle(new)
+    h0 = omlp.warm_start(_bf16_params(p), np.asarray(Anew.T @ W), EPS)
+    assert rel_fro(got, h0) <= 2e-2
+    # the two-GEMM route on the library's own rows of A_new^T W
+    R = torch.zeros(new.rows, K, device=cuda)
+    plan.foldin(M, R, init="wta", n_sweeps=0, trace=False)  # max(eps, A_new^T W)
+    nrm = R.norm(dim=1, keepdim=True)
+    y = net.forward(R / nrm)
+    ref = _np(torch.clamp(nrm * y, min=EPS))
+    assert rel_fro(got, ref) <= 1e-3
+    d = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-6 * np.abs(ref).max())
+    assert d.max() <= 3e-2
+    plan.close()
+
+
 def test_mlp_gradients_match_oracle(cuda):
     import torch
 
