@@ -15,7 +15,7 @@ namespace plnmf {
 // BF16 (2^-9) right after.
 __device__ __forceinline__ float erf_as(float x) {
   const float ax = fabsf(x);
-  const float t = __frcp_rn(1.0f + 0.3275911f * ax);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);  // hardware reciprocal, 1 ulp
   const float poly =
       t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f +
                                                                         t * 1.061405429f))));
@@ -25,8 +25,15 @@ __device__ __forceinline__ float erf_as(float x) {
 __device__ __forceinline__ float gelu_f(float z) {
   return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
 }
+// softplus(z) = max(z, 0) + log1p(exp(-|z|)), with log1p(u) = log(w) u / (w - 1),
+// w = 1 + u rounded (exact to a few ulp; Goldberg's correction), on the
+// hardware exponential and logarithm: the library log1pf expands to a long
+// compensated sequence, and this runs on every output of the network.
 __device__ __forceinline__ float softplus_f(float z) {
-  return z > 20.0f ? z : log1pf(expf(z));
+  const float u = __expf(-fabsf(z));
+  const float w = 1.0f + u;
+  const float l = w == 1.0f ? u : __logf(w) * u * __builtin_amdgcn_rcpf(w - 1.0f);
+  return fmaxf(z, 0.0f) + l;
 }
 
 

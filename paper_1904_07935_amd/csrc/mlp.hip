@@ -187,27 +187,35 @@ __global__ __launch_bounds__(512) void mlp_infer_kernel(MlpInferArgs a) {
   const int64_t row = r0 + m;
   const bf16x8 zero8 = {};
 
-  // this lane's pieces of its row, the row's norm, and x in BF16
+  // this lane's pieces of its row, the row's norm, and x in BF16 (the row is
+  // read twice, the second time from the L2, so that the FP32 values and x
+  // are never held together)
   bf16x8 xf[NKB];
   {
-    floatx4 v[NKB][2];
+    auto piece = [&](int s, int q) -> floatx4 {
+      const int k = 16 * s + 8 * h + 4 * q;
+      return (row < a.N && k < K) ? *(const floatx4*)(a.R + row * K + k) : floatx4{0, 0, 0, 0};
+    };
     float ss = 0.0f;
 #pragma unroll
     for (int s = 0; s < NKB; s++)
 #pragma unroll
       for (int q = 0; q < 2; q++) {
-        const int k = 16 * s + 8 * h + 4 * q;
-        v[s][q] = (row < a.N && k < K) ? *(const floatx4*)(a.R + row * K + k) : floatx4{0, 0, 0, 0};
+        const floatx4 v = piece(s, q);
 #pragma unroll
-        for (int e = 0; e < 4; e++) ss += v[s][q][e] * v[s][q][e];
+        for (int e = 0; e < 4; e++) ss += v[e] * v[e];
       }
     ss += __shfl_xor(ss, 32);
     const float nrm = sqrtf(ss);
+    const float inv = nrm > 0.0f ? 1.0f / nrm : 0.0f;
 #pragma unroll
     for (int s = 0; s < NKB; s++)
 #pragma unroll
-      for (int e = 0; e < 8; e++)
-        xf[s][e] = (__bf16)(nrm > 0.0f ? v[s][e >> 2][e & 3] / nrm : 0.0f);
+      for (int q = 0; q < 2; q++) {
+        const floatx4 v = piece(s, q);
+#pragma unroll
+        for (int e = 0; e < 4; e++) xf[s][4 * q + e] = (__bf16)(v[e] * inv);
+      }
     if (h == 0) nrs[32 * w + m] = nrm;
   }
 
@@ -254,15 +262,20 @@ __global__ __launch_bounds__(512) void mlp_infer_kernel(MlpInferArgs a) {
     put();
     __syncthreads();
     if (c + 1 < nch) fetch(c + 1);
-    // W1 x for the chunk's 32 hidden units
-    floatx16 acc1;
+    // W1 x for the chunk's 32 hidden units: even and odd steps in two
+    // accumulator chains (one chain would wait out every product's latency)
+    floatx16 acc1, acc1b;
 #pragma unroll
-    for (int e = 0; e < 16; e++) acc1[e] = 0.0f;
+    for (int e = 0; e < 16; e++) acc1[e] = acc1b[e] = 0.0f;
 #pragma unroll
     for (int s = 0; s < NKB; s++) {
       const bf16x8 wb = *(const bf16x8*)(w1s + m * KP1 + 16 * s + 8 * h);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wb, acc1, 0, 0, 0);
+      if (s & 1)
+        acc1b = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wb, acc1b, 0, 0, 0);
+      else
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xf[s], wb, acc1, 0, 0, 0);
     }
+    acc1 += acc1b;
     // bias + GELU; lane holds rows 8 jj + 4 h + i of hidden unit m
     {
       const float bb = a.b1[c * kHC + m];
