@@ -247,7 +247,9 @@ hipError_t acc_scaled(double* acc, const double* v, double scale, hipStream_t s)
 hipError_t mlp_out_grad(const float* z2, const float* yhat, const float* y, int64_t n,
                         float scale, __bf16* dz2_bf16, float* dz2_f32, double* loss_partial,
                         int nblk, hipStream_t s);
-hipError_t col_sum(const float* x, int64_t rows, int64_t cols, float* out, hipStream_t s);
+constexpr int kColSlices = 32;  // row slices of a column sum (part: kColSlices x cols doubles)
+hipError_t col_sum(const float* x, int64_t rows, int64_t cols, float* out, double* part,
+                   hipStream_t s);
 
 hipError_t gather_rows(const float* x, const int32_t* idx, int64_t n, int64_t cols, float* out,
                        hipStream_t s);

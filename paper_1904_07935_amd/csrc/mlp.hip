@@ -3,6 +3,8 @@
 // bias/softplus and GELU-gradient epilogues): seeded init, the output-layer
 // gradient of the mean-squared error, bias-gradient column sums, Adam, and the
 // row normalisation / rescaling that wraps the network in fold-in.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace plnmf {
@@ -73,13 +75,27 @@ __global__ void out_grad_kernel(const float* __restrict__ z2, const float* __res
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// out[c] = sum_r x[r, c], rows in order per column (FP64 accumulation)
-__global__ void colsum_kernel(const float* __restrict__ x, int64_t rows, int64_t cols,
-                              float* __restrict__ out) {
+// out[c] = sum_r x[r, c] in two fixed-order passes: slice s of the rows sums
+// its rows in order per column (FP64) into part[s][c], then the slices are
+// added in slice order.  Thread per column and workgroup per (column block,
+// row slice), so a batch of 1024 rows and 512 columns spreads over the chip.
+__global__ void colsum_part_kernel(const float* __restrict__ x, int64_t rows, int64_t cols,
+                                   int slices, double* __restrict__ part) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = blockIdx.y;
+  if (c >= cols) return;
+  const int64_t r0 = rows * sl / slices, r1 = rows * (sl + 1) / slices;
+  double s = 0.0;
+  for (int64_t r = r0; r < r1; r++) s += x[r * cols + c];
+  part[(int64_t)sl * cols + c] = s;
+}
+
+__global__ void colsum_fin_kernel(const double* __restrict__ part, int64_t cols, int slices,
+                                  float* __restrict__ out) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   double s = 0.0;
-  for (int64_t r = 0; r < rows; r++) s += x[r * cols + c];
+  for (int sl = 0; sl < slices; sl++) s += part[(int64_t)sl * cols + c];
   out[c] = (float)s;
 }
 
@@ -350,8 +366,13 @@ hipError_t mlp_out_grad(const float* z2, const float* yhat, const float* y, int6
   return hipGetLastError();
 }
 
-hipError_t col_sum(const float* x, int64_t rows, int64_t cols, float* out, hipStream_t s) {
-  colsum_kernel<<<(unsigned)((cols + 255) / 256), 256, 0, s>>>(x, rows, cols, out);
+hipError_t col_sum(const float* x, int64_t rows, int64_t cols, float* out, double* part,
+                   hipStream_t s) {
+  if (cols <= 0) return hipSuccess;
+  const int slices = (int)std::max<int64_t>(1, std::min<int64_t>(kColSlices, rows));
+  const unsigned cb = (unsigned)((cols + 255) / 256);
+  colsum_part_kernel<<<dim3(cb, (unsigned)slices), 256, 0, s>>>(x, rows, cols, slices, part);
+  colsum_fin_kernel<<<cb, 256, 0, s>>>(part, cols, slices, out);
   return hipGetLastError();
 }
 

@@ -71,6 +71,7 @@ struct Ws {
   float* partial;
   double* red;
   double* scal;
+  double* csum;  // column-sum partials [kColSlices][max(K, H)]
   float* grads;
   float* xbat;
   float* ybat;
@@ -101,6 +102,7 @@ Ws ws_layout(void* base, int K, int H, int64_t B) {
   w.partial = c.take<float>((size_t)std::max(sp, 1) * K * H);
   w.red = c.take<double>(1024);
   w.scal = c.take<double>(8);
+  w.csum = c.take<double>((size_t)kColSlices * std::max(K, H));
   w.grads = c.take<float>((size_t)H * K + H + (size_t)K * H + K);
   w.xbat = c.take<float>((size_t)(B * K));
   w.ybat = c.take<float>((size_t)(B * K));
@@ -207,7 +209,7 @@ int loss_grad_rows(const Params& p, int K, int H, const float* X, const float* Y
   a.splits = gemm_pick_splits(a.M, a.N, a.Kd, &a.k_per_split);
   a.partial = w.partial;
   MLPCHECK(gemm(Elem::BF16, true, false, a, s));
-  MLPCHECK(col_sum(w.dz2f, b, K, gb2, s));
+  MLPCHECK(col_sum(w.dz2f, b, K, gb2, w.csum, s));
   // dz1 [b,H] = (dz2 W2) * GELU'(z1)
   GemmArgs d{};
   d.A = w.dz2b;
@@ -240,7 +242,7 @@ int loss_grad_rows(const Params& p, int K, int H, const float* X, const float* Y
   c.splits = gemm_pick_splits(c.M, c.N, c.Kd, &c.k_per_split);
   c.partial = w.partial;
   MLPCHECK(gemm(Elem::BF16, true, false, c, s));
-  MLPCHECK(col_sum(w.dz1f, b, H, gb1, s));
+  MLPCHECK(col_sum(w.dz1f, b, H, gb1, w.csum, s));
   return NMF_OK;
 }
 
