@@ -185,12 +185,14 @@ def test_sparse_parity(cuda, K):
     plan.close()
 
 
-@pytest.mark.parametrize("K", [12, 150, 200, 300])
+@pytest.mark.parametrize("K", [12, 150, 200, 300, 302, 400])
 def test_sparse_products_with_empty_rows_and_columns(cuda, K):
     """CSR with empty rows (terms never used) and empty columns (documents with
     no terms) and one long row spanning many nnz chunks.  K covers the narrow
     (several nonzeros per wave step) and the wide (one nonzero per step,
-    prefetched item) product kernels, with and without 16-byte rows."""
+    prefetched item) product kernels, with and without 16-byte rows, and
+    (K > 256) R formed in two column slices of W, one of them of a width that
+    is not a multiple of four at K = 302."""
     rng = np.random.default_rng(5)
     V, D = 700, 500
     dense = (rng.random((V, D)) < 0.02) * rng.random((V, D))
