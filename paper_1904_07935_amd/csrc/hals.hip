@@ -96,24 +96,27 @@ __device__ __forceinline__ float wave_sum(float v) {
   return ((r0 + r1) + r2) + r3;
 }
 
-// The same as collect_sum for at most 64 groups (one slot per lane), with the
-// lanes summed by wave_sum.
+// The same as collect_sum for at most 128 groups (slots lane and lane + 64
+// per lane; on 256 CUs the product role's LDS admits at most 85 groups), with each lane's pair added in slot order and the lanes summed by
+// wave_sum: a fixed order, the same in every group.
 __device__ __forceinline__ float collect_sum64(const unsigned long long* slots, int groups, int g,
                                                unsigned tag, int par, int32_t* status) {
   const int lane = threadIdx.x & 63;
   const unsigned long long* p =
       slots + (int64_t)(g % kSlotReplicas) * kSlotStride + (int64_t)par * groups + lane;
-  const bool act = lane < groups;
-  unsigned long long v = (unsigned long long)tag << 32;  // inactive lanes: ready, zero
+  const bool act0 = lane < groups, act1 = lane + 64 < groups;
+  unsigned long long v0 = (unsigned long long)tag << 32;  // inactive slots: ready, zero
+  unsigned long long v1 = v0;
   int spins = 0;
   bool done;
   do {
-    if (act) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    done = __all((unsigned)(v >> 32) == tag);
+    if (act0) v0 = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (act1) v1 = __hip_atomic_load(p + 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    done = __all((unsigned)(v0 >> 32) == tag && (unsigned)(v1 >> 32) == tag);
     if (!done && (++spins & 255) == 0 && timed_out(status)) break;
   } while (!done && spins < kSpinLimit);
   if (!done && lane == 0) atomicOr(status, 256);
-  return wave_sum(__uint_as_float((unsigned)v));
+  return wave_sum(__uint_as_float((unsigned)v0) + __uint_as_float((unsigned)v1));
 }
 
 // Bounded wait of one wave until flags[i * stride], i < n, all hold `tag`.
@@ -773,7 +776,7 @@ constexpr int kWRowThreads = kWThreads - 64;        // wave 0 of a column group 
 constexpr int kWMaxRpt = 4;                         // rows per row thread of a column group
 constexpr int kWMaxRows = kWRowThreads * kWMaxRpt;  // rows per column group
 constexpr size_t kWSmemMin = 82 * 1024;             // > half the LDS: one group per CU
-constexpr int kWMaxColGroups = 64;
+constexpr int kWMaxColGroups = 128;
 
 // LDS (floats).  Column role: gt [T][TP] | wave sums [2][kWWaves] (in 2 kWWaves u64) |
 // column totals [2] (in 2 u64) | protocol flag [2] (u64) | lane partials
@@ -831,7 +834,7 @@ constexpr int kSlotDev = 0;      // [2][n_col] group partials (device scope)
 constexpr int kSlotPlace = 256;  // [n_col] XCD of each column group (device scope)
 constexpr int kSlotXcd = 512;    // [2 parities][2 replicas][64] group partials (XCD-local)
 static_assert(kSlotXcd + 2 * 128 <= kSlotWords, "slot regions");
-static_assert(kWMaxColGroups <= 64, "one slot per lane");
+static_assert(kWMaxColGroups <= 128, "two slots per lane");
 static_assert(kWMaxColGroups <= 256 - kSlotDev / 2, "slot regions");
 
 
@@ -1062,18 +1065,22 @@ __device__ __forceinline__ void w_column_role(const HalsWArgs a, int rank, int n
       if (lane == 0)
         __hip_atomic_store(a.slots + kSlotPlace + rank, pack_slot(ptag, __uint_as_float(xcc)),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      unsigned long long v = (unsigned long long)ptag << 32;
+      unsigned long long v = (unsigned long long)ptag << 32, v1 = v;
       int spins = 0;
       bool done;
       do {
         if (lane < a.n_col)
           v = __hip_atomic_load(a.slots + kSlotPlace + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        done = __all((unsigned)(v >> 32) == ptag);
+        if (lane + 64 < a.n_col)
+          v1 = __hip_atomic_load(a.slots + kSlotPlace + 64 + lane, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        done = __all((unsigned)(v >> 32) == ptag && (unsigned)(v1 >> 32) == ptag);
         if (!done && (++spins & 255) == 0 && timed_out(a.status)) break;
       } while (!done && spins < kSpinLimit);
       if (!done && lane == 0) atomicOr(a.status, 256);
       const unsigned first = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 0);
-      const bool same = __all(lane >= a.n_col || (unsigned)v == first);
+      const bool same = __all((lane >= a.n_col || (unsigned)v == first) &&
+                              (lane + 64 >= a.n_col || (unsigned)v1 == first));
       if (lane == 0) *lflag = same;
     }
     __syncthreads();
