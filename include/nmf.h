@@ -104,8 +104,8 @@ int nmf_workspace_bytes(const nmf_matrix* A, int K, int precision, size_t* bytes
  * Errors: NMF_E_NUMERIC for a negative/NaN/Inf entry of A, W or Ht, for an
  * all-zero A, or for a column of W with zero norm (it cannot be normalised);
  * NMF_E_UNSUPPORTED when the W update cannot hold V rows with all its
- * workgroups resident: column groups of at most 1,792 rows, each with two
- * product groups, one workgroup per CU (V <= 152,320 on 256 CUs).           */
+ * workgroups resident: at most 128 column groups of 1,792 rows, each with at
+ * least one product group, one workgroup per CU (V <= 229,376 on 256 CUs).  */
 int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision,
              float* W, float* Ht, void* workspace, size_t workspace_bytes, void* stream);
 

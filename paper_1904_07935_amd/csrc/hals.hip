@@ -97,7 +97,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // The same as collect_sum for at most 128 groups (slots lane and lane + 64
-// per lane; on 256 CUs the product role's LDS admits at most 85 groups), with each lane's pair added in slot order and the lanes summed by
+// per lane), with each lane's pair added in slot order and the lanes summed by
 // wave_sum: a fixed order, the same in every group.
 __device__ __forceinline__ float collect_sum64(const unsigned long long* slots, int groups, int g,
                                                unsigned tag, int par, int32_t* status) {
@@ -1182,9 +1182,9 @@ template <bool VEC>
 __device__ __forceinline__ void w_product_role(const HalsWArgs a, int prank, int n_prod, float* lds) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, h = lane >> 5, c = lane & 31;
   const int K = a.K;
-  const int jpw = a.jobs_per_wave;
+  const int jpw = a.jobs_per_wave, jpk = a.jobs_parked;      // jpk <= jpw
   float* bp = lds;                                            // [kpad(K)][TP]
-  float* stash = lds + kpad(K) * TP + w * jpw * 32 * TP;      // this wave's [jpw][32][TP]
+  float* stash = lds + kpad(K) * TP + w * jpk * 32 * TP;      // this wave's [jpk][32][TP]
   const int64_t rows = a.rows;
   const int g = prank % a.n_col, gi = prank / a.n_col;
   const int npg = (n_prod - g + a.n_col - 1) / a.n_col;       // product groups serving g
@@ -1211,8 +1211,10 @@ __device__ __forceinline__ void w_product_role(const HalsWArgs a, int prank, int
       }
     }
     __syncthreads();
-    // before the wait: Bterm plus every segment but the previous tile's
-    for (int k = 0; k < jpw; k++) {
+    // before the wait: Bterm plus every segment but the previous tile's, for
+    // the jobs the LDS can park (all of them unless the rows per product
+    // group are many and K large)
+    for (int k = 0; k < jpk; k++) {
       const int64_t lb = ((int64_t)k * kWWaves + w) * npg + gi;
       if (lb >= nblk) break;
       const int64_t job = blk0 + lb;
@@ -1238,8 +1240,25 @@ __device__ __forceinline__ void w_product_role(const HalsWArgs a, int prank, int
       const int64_t lb = ((int64_t)k * kWWaves + w) * npg + gi;
       if (lb >= nblk) break;
       const int64_t job = blk0 + lb;
-      float* st = stash + k * 32 * TP;
-      if (j > 0) {
+      float* st = stash + (k % jpk) * 32 * TP;  // a later job reuses a stored job's slot
+      if (k >= jpk) {
+        // not parked: the whole product now, the previous tile's columns included
+        floatx16 acc;
+#pragma unroll
+        for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+          for (int i = 0; i < 4; i++) {
+            const int64_t rg = job * 32 + 8 * jj + 4 * h + i;
+            acc[4 * jj + i] = (c < tw && rg < rows) ? a.Bterm[rg * K + a0 + c] : 0.0f;
+          }
+        const int64_t r = job * 32 + c;
+        const bool rok = r < rows;
+        block_segments<VEC>(acc, a, rok ? r : 0, rok, j, nseg, -1, bp, lane);
+#pragma unroll
+        for (int jj = 0; jj < 4; jj++)
+#pragma unroll
+          for (int i = 0; i < 4; i++) st[(8 * jj + 4 * h + i) * TP + c] = c < tw ? acc[4 * jj + i] : 0.0f;
+      } else if (j > 0) {
         const int64_t r = job * 32 + c;
         floatx4 last[4];
         load_segment<VEC>(last, a, r < rows ? r : 0, r < rows, j, j - 1, h);
@@ -1385,12 +1404,21 @@ int hals_w_rows_per_group(int64_t rows, int n_col) {
   return (int)((r + 31) / 32 * 32);
 }
 
+// Jobs per wave the product role parks in LDS before its wait (the rest are
+// computed whole after it): as many as fit beside the tile's panel.
+int jobs_parked(int K, int jpw) {
+  int p = jpw;
+  while (p > 1 && w_smem_bytes(K, p) > kLdsMax) p--;
+  return p;
+}
+
 int hals_w_grid(int device_cus, int64_t rows, int K, int n_col) {
   const int grid = device_cus;  // one group per CU (the LDS request admits no second one)
   if (n_col < 1 || 2 * n_col > grid || grid > kWFlagCol) return 0;
   const int jpw = jobs_per_wave(hals_w_rows_per_group(rows, n_col), grid, n_col);
-  const size_t bytes = w_smem_bytes(K, jpw < 1 ? 1 : jpw);
-  if (jpw < 1 || bytes > kLdsMax) return 0;
+  if (jpw < 1) return 0;
+  const size_t bytes = w_smem_bytes(K, jobs_parked(K, jpw));
+  if (bytes > kLdsMax) return 0;
   for (int rpt : {1, 2, 4})
     for (bool vec : {false, true})
       for (bool local : {false, true}) {
@@ -1413,8 +1441,10 @@ hipError_t hals_w_update(const HalsWArgs& a, int grid, hipStream_t s) {
   if (!a.panel) return hipErrorInvalidValue;
   HalsWArgs b = a;
   b.jobs_per_wave = jobs_per_wave(a.rows_per_group, grid, a.n_col);
-  const size_t bytes = w_smem_bytes(a.K, b.jobs_per_wave);
-  if (b.jobs_per_wave < 1 || bytes > kLdsMax) return hipErrorInvalidValue;
+  if (b.jobs_per_wave < 1) return hipErrorInvalidValue;
+  b.jobs_parked = jobs_parked(a.K, b.jobs_per_wave);
+  const size_t bytes = w_smem_bytes(a.K, b.jobs_parked);
+  if (bytes > kLdsMax) return hipErrorInvalidValue;
   const int rpt = (a.rows_per_group + kWRowThreads - 1) / kWRowThreads;
   const bool vec = (a.K % 4 == 0) && (((uintptr_t)a.X & 15) == 0);
   const void* fn = w_kernel_for(rpt, vec, a.n_col == 1);

@@ -227,6 +227,7 @@ struct HalsWArgs {
   int32_t* status;            // bit 8 set on a wait timeout
   const float* panel;         // tile panels of Q (gram_xtx with panel output, diag_one 0)
   int jobs_per_wave;          // set by hals_w_update
+  int jobs_parked;            // of those, parked in LDS before the wait (set by hals_w_update)
 };
 hipError_t hals_w_update(const HalsWArgs& a, int grid, hipStream_t s);
 int hals_w_max_rows_per_group();

@@ -149,16 +149,18 @@ def test_w_column_groups_across_xcds_match_oracle(cuda, monkeypatch):
     plan.close()
 
 
-@pytest.mark.parametrize("V, groups", [(40000, 32), (60000, 34), (150000, 84), (152320, 85)])
-def test_w_half_four_rows_per_thread_matches_oracle(cuda, V, groups):
+@pytest.mark.parametrize("V, groups, K", [(40000, 32, 48), (60000, 34, 48), (150000, 84, 48),
+                                           (229376, 128, 48), (150000, 84, 256)])
+def test_w_half_four_rows_per_thread_matches_oracle(cuda, V, groups, K):
     """Corpora large enough that a column group holds more than two rows per
     thread (the four-row variant of the W kernel): 32 column groups on one XCD
     (the XCD-local exchange), 34 groups, more than one XCD holds (the
-    device-scope exchange), and 84 and 85 groups, more than one slot per
-    polling lane (85 x 1792 rows, with two product groups per column group on
-    256 CUs, is the kernel's largest V).  One W half against the oracle's."""
-    c = datagen.bag_of_words(V, 6000, 1.1, 77.0, 7)
-    K = 48
+    device-scope exchange), 84 and 128 groups, more than one slot per polling
+    lane (128 x 1792 rows is the kernel's largest V; there each product group
+    serves one column group and parks only part of its row blocks in LDS
+    before its wait), and 84 groups at K = 256, where the tile panel leaves
+    room to park three of four blocks.  One W half against the oracle's."""
+    c = datagen.bag_of_words(V, 6000 if K < 100 else 2000, 1.1, 77.0, 7)
     W0, H0 = sparse_init(c, K)
     plan = gpu_plan(c.A, W0, H0, cuda)
     assert plan.info()["w_groups"] == groups
@@ -172,11 +174,11 @@ def test_w_half_four_rows_per_thread_matches_oracle(cuda, V, groups):
 
 
 def test_w_kernel_rejects_more_rows_than_it_holds(cuda):
-    """V beyond what the W kernel holds (85 column groups of 1792 rows on 256
-    CUs): nmf_init refuses the plan with NMF_E_UNSUPPORTED instead of
-    launching a W update that cannot hold it."""
+    """V beyond what the W kernel holds (128 column groups of 1792 rows):
+    nmf_init refuses the plan with NMF_E_UNSUPPORTED instead of launching a W
+    update that cannot hold it."""
     from paper_1904_07935_amd._lib import NmfError
-    c = datagen.bag_of_words(152321, 2000, 1.1, 77.0, 9)
+    c = datagen.bag_of_words(229377, 2000, 1.1, 77.0, 9)
     W0, H0 = sparse_init(c, 8)
     with pytest.raises(NmfError) as e:
         gpu_plan(c.A, W0, H0, cuda)
