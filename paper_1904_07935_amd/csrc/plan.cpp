@@ -688,7 +688,7 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
     std::vector<uint8_t> skip;
     const int drm = dense_rows_mode();
     if (drm == 1 || (drm < 0 && s.D * (int64_t)K >= kDenseRowsMinDK)) {
-      // the densest rows of A (longer than one work item and at least 1/16
+      // the densest rows of A (longer than one work item and at least 1/24
       // dense; at most kDenseRowsMax, longest first) are multiplied as a dense
       // block on the matrix cores; the sparse product skips them.  Only when
       // H^T is large (D K >= 32M floats): then each gathered row mostly comes
@@ -702,7 +702,7 @@ int nmf_init(nmf_plan* out, const nmf_matrix* A, int K, float eps, int precision
       std::vector<int32_t> cand;
       for (int64_t r = 0; r < s.V; r++) {
         const int64_t len = (int64_t)rp[r + 1] - rp[r];
-        if (len > p->sp_A.L && len * 16 >= s.D) cand.push_back((int32_t)r);
+        if (len > p->sp_A.L && len * 24 >= s.D) cand.push_back((int32_t)r);
       }
       std::stable_sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
         return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];

@@ -25,7 +25,7 @@ int fail(int code, const char* fmt, ...);
   } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int kDenseRowsMax = 128;  // rows of A multiplied as a dense block in P = A H^T
+constexpr int kDenseRowsMax = 256;  // rows of A multiplied as a dense block in P = A H^T
 constexpr int64_t kDenseRowsMinDK = (int64_t)32 << 20;  // ... when D K reaches this
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
