@@ -241,6 +241,7 @@ int plnmf::foldin_run(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int in
   a.diag_one = 1;
   a.panel = f.panel;
   a.tile = p->h_tile;
+  a.cus = p->cus;
   int filled = 0;  // trace entries waiting in f.trace
   int written = 0; // trace entries copied to the host
   auto flush = [&]() -> int {

@@ -1326,16 +1326,23 @@ const void* w_kernel_for(int rpt, bool vec, bool local) {
 int hals_rows_per_group_h() { return kRowsH; }
 
 // Which H-update kernel.  The rows-in-registers kernel takes 128 rows per
-// workgroup and fills the chip from about 256 x 128 rows on; below that the
-// LDS-resident kernel (32 rows per workgroup) keeps more CUs busy.
+// workgroup and fills the chip from about 256 x 128 rows on.  Below that the
+// LDS-resident kernel (32 rows per workgroup) keeps more CUs busy, as long as
+// all its workgroups are resident at once; once they need a second round (its
+// LDS holds two workgroups per CU up to K = 224, one above), the rows kernel's
+// single round is shorter.  Measured on 11,000 rows: K = 200 LDS 48 us, rows
+// 64 us; K = 240 LDS 96 us, rows 76 us; K = 400 LDS 220 us, rows 161 us; on
+// 10,000 rows at K = 240: LDS 111 us, rows 79 us.
 // NMF_H_KERNEL=rows|lds forces one (read at every call: measurement, tests).
-static bool h_rows_kernel_for(int64_t rows, int K) {
-  (void)K;
+static bool h_rows_kernel_for(int64_t rows, int K, int cus) {
   if (const char* e = getenv("NMF_H_KERNEL")) {
     if (e[0] == 'r') return true;
     if (e[0] == 'l') return false;
   }
-  return rows >= 32768;
+  if (rows >= 32768) return true;
+  const int64_t per_cu = (int64_t)(kRrLdsMax / (h_smem_floats(K) * 4));
+  const int64_t groups = (rows + kRowsH - 1) / kRowsH;
+  return groups > (int64_t)(cus > 0 ? cus : 256) * per_cu;
 }
 
 size_t hals_panel_floats(int K, int tile) {
@@ -1362,7 +1369,7 @@ hipError_t hals_update(const HalsArgs& a, hipStream_t s) {
   const bool vec = (a.K % 4 == 0) && (((uintptr_t)a.X & 15) == 0);
   if (tile != T && !vec) return hipErrorInvalidValue;
   // widths other than 32: the rows-in-registers kernel only
-  if (tile != T || h_rows_kernel_for(a.rows, a.K)) return h_rows_dispatch(b, vec, s);
+  if (tile != T || h_rows_kernel_for(a.rows, a.K, a.cus)) return h_rows_dispatch(b, vec, s);
   const size_t bytes = h_smem_floats(a.K) * 4;
   const void* fn = vec ? (const void*)hals_h_kernel<true> : (const void*)hals_h_kernel<false>;
   hipError_t e = allow_smem(fn, bytes);

@@ -196,6 +196,7 @@ struct HalsArgs {
   const float* panel;    // tile panels of G (gram_xtx with panel output, diag_one and tile as here)
   const float* gblk;     // set by hals_update
   int tile;              // tile width: 32 (0 = 32), 16 or 64 (see hals_tile_supported)
+  int cus;               // compute units of the device (0: taken as 256), for the kernel choice
 };
 // Row-independent update (no normalisation): the H half and fold-in.
 hipError_t hals_update(const HalsArgs& a, hipStream_t s);

@@ -427,6 +427,7 @@ int half_h(nmf_plan_s* p) {
   a.diag_one = 1;
   a.panel = p->panel_h;
   a.tile = p->h_tile;
+  a.cus = p->cus;
   TIMED(p, NMF_STEP_UPDATE_H, hals_update(a, p->stream));
   p->pq_valid = false;
   return NMF_OK;
