@@ -522,7 +522,10 @@ template <int NT, int TT, bool VEC>
 __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
   constexpr int NB = rr_nb(TT), HP = TT / 2, PP = rr_pp(TT);
   extern __shared__ float smem_raw[];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, m = lane & 31, h = lane >> 5;
+  // w is the same in every lane of a wave: taken as such, the wave's row
+  // offsets and buffer views below stay scalar
+  const int tid = threadIdx.x, lane = tid & 63, m = lane & 31, h = lane >> 5;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int K = a.K, kp = kpad(K), ntiles = (K + TT - 1) / TT;
   float* lpb = smem_raw;                           // [2][NB * NT * 1024]
   float* gtb = lpb + 2 * NB * NT * 1024;           // [2][TT * TT]
@@ -542,43 +545,38 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
     rr_load<NT, TT>(a.panel, a.gblk, kp, 0, tid, st);
     rr_store<NT, TT>(st, lpb, gtb, tid);
   }
-  // the wave's rows into the A-operand layout, 32 columns at a time (the
-  // transpose goes through the first 32 x 33 floats of part)
+  // Buffer views of the wave's rows of X and of Bterm (nr rows of K floats):
+  // a load past the view returns zero, so rows beyond the matrix need no test,
+  // and the constant column offsets stay in the instructions.
+  const int64_t wave_bytes = nr > 0 ? (int64_t)nr * K * 4 : 0;
+  const __amdgpu_buffer_rsrc_t xv =
+      __builtin_amdgcn_make_buffer_rsrc(X + (nr > 0 ? row0 * K : 0), 0, (int)wave_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t bv = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(a.Bterm + (nr > 0 ? row0 * K : 0)), 0, (int)wave_bytes, 0x00020000);
+  // the wave's rows straight into the A-operand layout, all loads in flight
+  // at once: lane (m, h) reads X[row m][32 t + 2 s + h].  Columns past K
+  // (only in the last 32) hold the next row's values or zero and are cleared
+  // once every load is issued.
   float xa[16 * NT];
+  {
+    const uint32_t xo = (uint32_t)((m * K + h) * 4);
 #pragma unroll
-  for (int t = 0; t < NT; t++) {
-    if (lane < kRowsRR) {
+    for (int t = 0; t < NT; t++)
 #pragma unroll
-      for (int q = 0; q < 8; q++) {
-        const int c = 32 * t + 4 * q;
-        floatx4 v = floatx4{0, 0, 0, 0};
-        if (lane < nr) {
-          const float* src = X + (row0 + lane) * K + c;
-          if constexpr (VEC) {
-            if (c < K) v = *(const floatx4*)src;
-          } else {
+      for (int s2 = 0; s2 < 16; s2++)
+        xa[16 * t + s2] = __uint_as_float(
+            __builtin_amdgcn_raw_buffer_load_b32(xv, xo + (uint32_t)((32 * t + 2 * s2) * 4), 0, 0));
 #pragma unroll
-            for (int e = 0; e < 4; e++)
-              if (c + e < K) v[e] = src[e];
-          }
-        }
-#pragma unroll
-        for (int e = 0; e < 4; e++) part[lane * TP + 4 * q + e] = v[e];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s2 = 0; s2 < 16; s2++) xa[16 * t + s2] = part[m * TP + 2 * s2 + h];
-    __syncthreads();
+    for (int s2 = 0; s2 < 16; s2++)
+      if (32 * (NT - 1) + 2 * s2 + h >= K) xa[16 * (NT - 1) + s2] = 0.0f;
   }
-
-#pragma unroll 1
-  for (int j = 0; j < ntiles; j++) {
-    const int a0 = j * TT, tw = a0 + TT < K ? TT : K - a0;
-    const float* lp = lpb + (j & 1) * NB * NT * 1024;
-    const float* gt = gtb + (j & 1) * TT * TT;
-    // Bterm of the tile in the product's lane layout
-    float bt[NB][16];
+  // Bterm of a tile in the product's lane layout: lane (m, h) takes column
+  // a0 + 32 q + m of rows 8 jj + 4 h + i; loaded one tile ahead, into the
+  // registers the previous tile has just consumed, and not used until after
+  // that tile's product.  Columns past the tile's width are masked where
+  // the values are used.
+  float bt[NB][16];
+  auto load_bt = [&](int a0) {
 #pragma unroll
     for (int q = 0; q < NB; q++)
 #pragma unroll
@@ -586,8 +584,18 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
           const int rl = 8 * jj + 4 * h + i, c = 32 * q + m;
-          bt[q][4 * jj + i] = (rl < nr && c < tw) ? a.Bterm[(row0 + rl) * K + a0 + c] : 0.0f;
+          bt[q][4 * jj + i] = __uint_as_float(
+              __builtin_amdgcn_raw_buffer_load_b32(bv, (uint32_t)((rl * K + a0 + c) * 4), 0, 0));
         }
+  };
+  load_bt(0);
+  __syncthreads();  // tile 0's panel, staged above, is seen by every wave
+
+#pragma unroll 1
+  for (int j = 0; j < ntiles; j++) {
+    const int a0 = j * TT, tw = a0 + TT < K ? TT : K - a0;
+    const float* lp = lpb + (j & 1) * NB * NT * 1024;
+    const float* gt = gtb + (j & 1) * TT * TT;
     // the next tile's staging: global loads now, LDS stores after the product
     RrStage<NT, TT> st;
     if (j + 1 < ntiles) rr_load<NT, TT>(a.panel, a.gblk, kp, j + 1, tid, st);
@@ -619,7 +627,9 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; i++)
           if (32 * q + m < TT)
-            part[(8 * jj + 4 * h + i) * PP + 32 * q + m] = acc[q][4 * jj + i] + bt[q][4 * jj + i];
+            part[(8 * jj + 4 * h + i) * PP + 32 * q + m] =
+                32 * q + m < tw ? acc[q][4 * jj + i] + bt[q][4 * jj + i] : 0.0f;
+    if (j + 1 < ntiles) load_bt(a0 + TT);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
