@@ -88,8 +88,8 @@ FoldWs fold_layout(void* base, int64_t Dn, int64_t V, int K, const nmf_matrix* A
 }
 
 hipError_t gram_with(const float* X, int64_t rows, int K, float* out, float* gpart, int cus,
-                     hipStream_t s, float* panel = nullptr, int tile = 32) {
-  return gram_xtx(X, rows, K, out, K, gpart, gram_chunks(rows, cus), s, panel, 1, tile);
+                     hipStream_t s, float* panel = nullptr, int tile = 32, bool rows_layout = false) {
+  return gram_xtx(X, rows, K, out, K, gpart, gram_chunks(rows, cus), s, panel, 1, tile, rows_layout);
 }
 
 #define FCHECK(expr)                                                                      \
@@ -220,7 +220,8 @@ int plnmf::foldin_run(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int in
   FCHECK(hipMemsetAsync(f.panel, 0,
                         std::max(std::max(hals_panel_floats(K, 16), hals_panel_floats(K, 32)),
                                  hals_panel_floats(K, 64)) * sizeof(float), s));
-  FCHECK(gram_with(p->W, p->V, K, f.S, f.gpart, p->cus, s, f.panel, p->h_tile));
+  const bool rl = hals_h_rows_layout(Dn, K, p->cus, p->h_tile);
+  FCHECK(gram_with(p->W, p->V, K, f.S, f.gpart, p->cus, s, f.panel, p->h_tile, rl));
 
   // initialisation of H for the new documents
   if (init_mode == NMF_FOLDIN_WTA) {
@@ -241,7 +242,7 @@ int plnmf::foldin_run(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int in
   a.diag_one = 1;
   a.panel = f.panel;
   a.tile = p->h_tile;
-  a.cus = p->cus;
+  a.rows_layout = rl;
   int filled = 0;  // trace entries waiting in f.trace
   int written = 0; // trace entries copied to the host
   auto flush = [&]() -> int {

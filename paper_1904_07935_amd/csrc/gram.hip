@@ -144,6 +144,30 @@ constexpr int kRedThreads = 32 * kRedSlices;
 // operand of the tile of col, contraction row l): 1 - C or 0 on the diagonal,
 // 0 for l inside the tile and left of col, -C elsewhere.  Same layout as the
 // update kernels read: panel[j][l][c] (l < kpad(K), c < 32), then gblk[j][t][c].
+// The same entries in the H rows kernel's staging order, one block of
+// NB * NT * 1024 + tile^2 floats per tile (NT = ceil(K / 32), NB = max(1,
+// tile / 32)): entry (l, c) of the tile's panel at
+// ((((c / 32) NT + l / 32) 4 + s / 4) 2 + l % 2) 32 + c % 32) 4 + s % 4 with
+// s = (l % 32) / 2 -- lane (m, h) then reads rows 32 t + 2 (4 sq + i) + h of
+// column m as one float4 -- then the G block split by column parity,
+// [h][t][k] = G[t][2 k + h] where 2 k + h > t (zero elsewhere).
+__device__ __forceinline__ void put_panel_rows(float* panel, int K, int diag_one, int tile, int l, int col,
+                                               float v) {
+  const int nt = (K + 31) / 32, nb = tile >= 32 ? tile / 32 : 1;
+  const int64_t per_tile = (int64_t)nb * nt * 1024 + tile * tile;
+  const int j = col / tile, c = col % tile, a0 = tile * j;
+  float pv;
+  if (l == col) pv = diag_one ? 1.0f - v : 0.0f;
+  else if (l >= a0 && l < col) pv = 0.0f;
+  else pv = -v;
+  const int r = l & 31, s2 = r >> 1;
+  float* pt = panel + j * per_tile;
+  pt[(((((c >> 5) * nt + (l >> 5)) * 4 + (s2 >> 2)) * 2 + (r & 1)) * 32 + (c & 31)) * 4 + (s2 & 3)] = pv;
+  const int t = l - a0;
+  if (l / tile == j && c > t)
+    pt[(int64_t)nb * nt * 1024 + (c & 1) * (tile * tile / 2) + t * (tile / 2) + (c >> 1)] = v;
+}
+
 __device__ __forceinline__ void put_panel(float* panel, int K, int diag_one, int tile, int l, int col,
                                           float v) {
   const int kp = (K + 7) / 8 * 8, ntiles = (K + tile - 1) / tile;
@@ -159,7 +183,8 @@ __device__ __forceinline__ void put_panel(float* panel, int K, int diag_one, int
 
 __global__ __launch_bounds__(kRedThreads) void gram_reduce(const float* __restrict__ partial, int nchunks,
                                                     int K, float* __restrict__ C, int64_t ldc,
-                                                    float* __restrict__ panel, int diag_one, int tile) {
+                                                    float* __restrict__ panel, int diag_one, int tile,
+                                                    int rows_layout) {
   __shared__ floatx4 part[kRedThreads];
   const int nb = nblk(K), nu = upper_blocks(K);
   const int u = blockIdx.x / 8, piece = blockIdx.x % 8;
@@ -201,7 +226,10 @@ __global__ __launch_bounds__(kRedThreads) void gram_reduce(const float* __restri
       if (gi < K && gj < K) {
         C[(int64_t)gi * ldc + gj] = tot[e];
         if (bi != bj) C[(int64_t)gj * ldc + gi] = tot[e];
-        if (panel) {
+        if (panel && rows_layout) {
+          put_panel_rows(panel, K, diag_one, tile, gi, gj, tot[e]);
+          if (bi != bj) put_panel_rows(panel, K, diag_one, tile, gj, gi, tot[e]);
+        } else if (panel) {
           put_panel(panel, K, diag_one, tile, gi, gj, tot[e]);
           if (bi != bj) put_panel(panel, K, diag_one, tile, gj, gi, tot[e]);
         }
@@ -226,7 +254,7 @@ int gram_chunks(int64_t rows, int device_cus) {
 size_t gram_partial_floats(int K, int chunks) { return (size_t)chunks * upper_blocks(K) * 1024; }
 
 hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, float* partial,
-                    int chunks, hipStream_t s, float* panel, int diag_one, int tile) {
+                    int chunks, hipStream_t s, float* panel, int diag_one, int tile, bool rows_layout) {
   if (K <= 0) return hipSuccess;
   if (K > kMaxK || chunks < 1) return hipErrorInvalidValue;
   const int64_t rpc = (rows + chunks - 1) / chunks;
@@ -244,7 +272,7 @@ hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   gram_reduce<<<(unsigned)(upper_blocks(K) * 8), kRedThreads, 0, s>>>(partial, chunks, K, C, ldc, panel,
-                                                                diag_one, tile);
+                                                                diag_one, tile, rows_layout ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -462,59 +462,45 @@ __host__ __device__ inline size_t rr_smem_floats(int NT, int TT) {
 }
 constexpr size_t kRrLdsMax = 160 * 1024;
 
-// Tile j's staging: the panel (kpad(K) rows of TT, zeros up to 32 NT rows) in
+// Tile j's staging block, as the Gram writes it for this kernel: the panel in
 // lane-read order -- float4 (((q NT + t) 4 + sq) 2 + h) 32 + m holds rows
-// 32 t + 2 (4 sq + i) + h of column 32 q + m -- and the G block split by
-// column parity, gh[h][t][k] = G[t][2 k + h] for 2 k + h > t, else 0 (the
-// columns a phase-2 step updates).  Loads are issued by rr_load (early),
-// stores by rr_store.
+// 32 t + 2 (4 sq + i) + h of column 32 q + m (zeros past K) -- then the G
+// block split by column parity, gh[h][t][k] = G[t][2 k + h] for 2 k + h > t,
+// else 0 (the columns a phase-2 step updates).  A contiguous copy into the
+// LDS: loads are issued by rr_load (early), stores by rr_store.
+__host__ __device__ inline size_t rr_stage_floats(int NT, int TT) {
+  return (size_t)rr_nb(TT) * NT * 1024 + (size_t)TT * TT;
+}
 template <int NT, int TT>
 struct RrStage {
-  static constexpr int NP = (NT * 32 * (TT / 4) + 255) / 256;
-  static constexpr int NG = (TT * TT + 255) / 256;
+  static constexpr int NP = rr_nb(TT) * NT;             // float4 of the panel per thread
+  static constexpr int NG = (TT * TT / 4 + 255) / 256;  // float4 of the G block per thread
   floatx4 v[NP];
-  float g[NG];
+  floatx4 g[NG];
 };
 
 template <int NT, int TT>
-__device__ __forceinline__ void rr_load(const float* __restrict__ panel, const float* __restrict__ gblk,
-                                        int kp, int j, int tid, RrStage<NT, TT>& st) {
-  constexpr int Q4 = TT / 4, N4 = NT * 32 * Q4, NP = RrStage<NT, TT>::NP;
-  const floatx4* src = (const floatx4*)(panel + (int64_t)j * kp * TT);
+__device__ __forceinline__ void rr_load(const float* __restrict__ panel, int j, int tid,
+                                        RrStage<NT, TT>& st) {
+  const floatx4* src = (const floatx4*)(panel + (int64_t)j * rr_stage_floats(NT, TT));
 #pragma unroll
-  for (int k = 0; k < NP; k++) {
-    const int i = tid + 256 * k, l = i / Q4;
-    st.v[k] = (i < N4 && l < kp) ? src[i] : floatx4{0, 0, 0, 0};
-  }
-  const float* gs = gblk + (int64_t)j * TT * TT;
+  for (int k = 0; k < RrStage<NT, TT>::NP; k++) st.v[k] = src[tid + 256 * k];
+  const floatx4* gs = src + rr_nb(TT) * NT * 256;
 #pragma unroll
   for (int k = 0; k < RrStage<NT, TT>::NG; k++) {
-    const int idx = tid + 256 * k, h = idx / (TT * TT / 2), t = (idx / (TT / 2)) % TT,
-              kk = idx % (TT / 2), c = 2 * kk + h;
-    st.g[k] = (idx < TT * TT && c > t) ? gs[t * TT + c] : 0.0f;
+    const int idx = tid + 256 * k;
+    st.g[k] = idx < TT * TT / 4 ? gs[idx] : floatx4{0, 0, 0, 0};
   }
 }
 
 template <int NT, int TT>
 __device__ __forceinline__ void rr_store(const RrStage<NT, TT>& st, float* lp, float* gt, int tid) {
-  constexpr int Q4 = TT / 4, N4 = NT * 32 * Q4, NP = RrStage<NT, TT>::NP;
 #pragma unroll
-  for (int k = 0; k < NP; k++) {
-    const int i = tid + 256 * k;
-    if (i < N4) {
-      const int l = i / Q4, c0 = 4 * (i % Q4), q = c0 >> 5, m0 = c0 & 31;
-      const int t = l >> 5, r = l & 31, s2 = r >> 1, h = r & 1, sq = s2 >> 2, ii = s2 & 3;
-      float* d = lp + (((((q * NT + t) * 4 + sq) * 2 + h) * 32 + m0) * 4) + ii;
-      d[0] = st.v[k][0];
-      d[4] = st.v[k][1];
-      d[8] = st.v[k][2];
-      d[12] = st.v[k][3];
-    }
-  }
+  for (int k = 0; k < RrStage<NT, TT>::NP; k++) ((floatx4*)lp)[tid + 256 * k] = st.v[k];
 #pragma unroll
   for (int k = 0; k < RrStage<NT, TT>::NG; k++) {
     const int idx = tid + 256 * k;
-    if (idx < TT * TT) gt[idx] = st.g[k];
+    if (idx < TT * TT / 4) ((floatx4*)gt)[idx] = st.g[k];
   }
 }
 
@@ -526,7 +512,7 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
   // offsets and buffer views below stay scalar
   const int tid = threadIdx.x, lane = tid & 63, m = lane & 31, h = lane >> 5;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int K = a.K, kp = kpad(K), ntiles = (K + TT - 1) / TT;
+  const int K = a.K, ntiles = (K + TT - 1) / TT;
   float* lpb = smem_raw;                           // [2][NB * NT * 1024]
   float* gtb = lpb + 2 * NB * NT * 1024;           // [2][TT * TT]
   float* part = gtb + 2 * TT * TT + w * 32 * PP;   // this wave's [32][TT + 1]
@@ -535,14 +521,9 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
   const float eps = a.eps;
   float* __restrict__ X = a.X;
 
-  if constexpr (TT < 32) {
-    // the panel columns a 16-wide tile leaves unused stay zero
-    for (int i = tid; i < 2 * NB * NT * 1024; i += 256) lpb[i] = 0.0f;
-    __syncthreads();
-  }
   {
     RrStage<NT, TT> st;
-    rr_load<NT, TT>(a.panel, a.gblk, kp, 0, tid, st);
+    rr_load<NT, TT>(a.panel, 0, tid, st);
     rr_store<NT, TT>(st, lpb, gtb, tid);
   }
   // Buffer views of the wave's rows of X and of Bterm (nr rows of K floats):
@@ -598,7 +579,7 @@ __global__ __launch_bounds__(256) void hals_h_rows_kernel(HalsArgs a) {
     const float* gt = gtb + (j & 1) * TT * TT;
     // the next tile's staging: global loads now, LDS stores after the product
     RrStage<NT, TT> st;
-    if (j + 1 < ntiles) rr_load<NT, TT>(a.panel, a.gblk, kp, j + 1, tid, st);
+    if (j + 1 < ntiles) rr_load<NT, TT>(a.panel, j + 1, tid, st);
     // the tile product over the whole contraction, B operand from LDS
     floatx16 acc[NB];
 #pragma unroll
@@ -1343,7 +1324,8 @@ int hals_rows_per_group_h() { return kRowsH; }
 // single round is shorter.  Measured on 11,000 rows: K = 200 LDS 48 us, rows
 // 64 us; K = 240 LDS 96 us, rows 76 us; K = 400 LDS 220 us, rows 161 us; on
 // 10,000 rows at K = 240: LDS 111 us, rows 79 us.
-// NMF_H_KERNEL=rows|lds forces one (read at every call: measurement, tests).
+// NMF_H_KERNEL=rows|lds forces one (read when the half starts: measurement,
+// tests).
 static bool h_rows_kernel_for(int64_t rows, int K, int cus) {
   if (const char* e = getenv("NMF_H_KERNEL")) {
     if (e[0] == 'r') return true;
@@ -1356,8 +1338,16 @@ static bool h_rows_kernel_for(int64_t rows, int K, int cus) {
 }
 
 size_t hals_panel_floats(int K, int tile) {
+  // the larger of the two orders: [tile][row][column] + the G blocks, or the
+  // rows kernel's staging blocks (rows padded to 32 NT)
   const int ntiles = (K + tile - 1) / tile;
-  return (size_t)ntiles * kpad(K) * tile + (size_t)ntiles * tile * tile;
+  const size_t plain = (size_t)ntiles * kpad(K) * tile + (size_t)ntiles * tile * tile;
+  const size_t rows = (size_t)ntiles * rr_stage_floats((K + 31) / 32, tile);
+  return plain > rows ? plain : rows;
+}
+
+bool hals_h_rows_layout(int64_t rows, int K, int cus, int tile) {
+  return (tile != 0 && tile != T) || h_rows_kernel_for(rows, K, cus);
 }
 
 bool hals_tile_supported(int K, int tile) {
@@ -1379,7 +1369,8 @@ hipError_t hals_update(const HalsArgs& a, hipStream_t s) {
   const bool vec = (a.K % 4 == 0) && (((uintptr_t)a.X & 15) == 0);
   if (tile != T && !vec) return hipErrorInvalidValue;
   // widths other than 32: the rows-in-registers kernel only
-  if (tile != T || h_rows_kernel_for(a.rows, a.K, a.cus)) return h_rows_dispatch(b, vec, s);
+  if (a.rows_layout) return h_rows_dispatch(b, vec, s);
+  if (tile != T) return hipErrorInvalidValue;  // other widths: the rows kernel only
   const size_t bytes = h_smem_floats(a.K) * 4;
   const void* fn = vec ? (const void*)hals_h_kernel<true> : (const void*)hals_h_kernel<false>;
   hipError_t e = allow_smem(fn, bytes);

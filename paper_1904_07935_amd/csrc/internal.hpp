@@ -100,10 +100,12 @@ int gram_max_chunks();
 size_t gram_partial_floats(int K, int chunks);
 // With `panel` set, also writes the tile panels of the column updates derived
 // from C (hals_panel_floats(K) floats; entries that never depend on C -- rows
-// >= K, and outside the last tile -- must have been zeroed once).
+// >= K, and outside the last tile -- must have been zeroed once), in the
+// [tile][row][column] order with the tiles' G blocks after them, or with
+// `rows_layout` in the H rows kernel's staging order (hals_h_rows_layout).
 hipError_t gram_xtx(const float* X, int64_t rows, int K, float* C, int64_t ldc, float* partial,
                     int chunks, hipStream_t s, float* panel = nullptr, int diag_one = 0,
-                    int tile = 32);
+                    int tile = 32, bool rows_layout = false);
 
 // ------------------------------------------------------------------ SpMM ----
 // out[r, 0:K] = sum_j val[j] X[col[j], 0:K] over the rows of a CSR matrix.
@@ -196,11 +198,15 @@ struct HalsArgs {
   const float* panel;    // tile panels of G (gram_xtx with panel output, diag_one and tile as here)
   const float* gblk;     // set by hals_update
   int tile;              // tile width: 32 (0 = 32), 16 or 64 (see hals_tile_supported)
-  int cus;               // compute units of the device (0: taken as 256), for the kernel choice
+  int rows_layout;       // panel written in the rows kernel's order: that kernel runs
 };
 // Row-independent update (no normalisation): the H half and fold-in.
 hipError_t hals_update(const HalsArgs& a, hipStream_t s);
 size_t hals_panel_floats(int K, int tile = 32);
+// Whether the H update of `rows` rows takes the rows-in-registers kernel (so
+// its Gram writes the panel in that kernel's staging order): decided once by
+// the caller, passed to gram_xtx and to hals_update (HalsArgs::rows_layout).
+bool hals_h_rows_layout(int64_t rows, int K, int cus, int tile);
 // Tile widths of the H update: 32 always; 16 and 64 when K % 4 == 0 and the
 // rows-in-registers kernel's double-buffered panel fits the LDS.
 bool hals_tile_supported(int K, int tile);

@@ -244,12 +244,13 @@ int plnmf::device_check(int* dev, int* cus) {
 }
 
 // ------------------------------------------------------- step launchers ----
-hipError_t plnmf::gram(nmf_plan_s* p, const float* X, int64_t rows, float* out, int panel_diag) {
-  // panel_diag 1: the H update's panels (its own buffer and tile width);
-  // 0: the W update's (32 wide)
+hipError_t plnmf::gram(nmf_plan_s* p, const float* X, int64_t rows, float* out, int panel_diag,
+                       bool rows_layout) {
+  // panel_diag 1: the H update's panels (its own buffer and tile width, in
+  // the order of the kernel that will read them); 0: the W update's (32 wide)
   float* panel = panel_diag == 1 ? p->panel_h : panel_diag == 0 ? p->panel : nullptr;
   return gram_xtx(X, rows, p->K, out, p->K, p->gram_part, gram_chunks(rows, p->cus), p->stream,
-                  panel, panel_diag, panel_diag == 1 ? p->h_tile : kTile);
+                  panel, panel_diag, panel_diag == 1 ? p->h_tile : kTile, panel_diag == 1 && rows_layout);
 }
 
 namespace {
@@ -415,7 +416,14 @@ void prof_clear(nmf_plan_s* p) {
 }
 
 int half_h(nmf_plan_s* p) {
-  TIMED(p, NMF_STEP_GRAM_S, gram(p, p->W, p->V, p->S, 1));  // + the H update's panels
+  const bool rl = hals_h_rows_layout(p->D, p->K, p->cus, p->h_tile);
+  if (p->h_panel_order >= 0 && p->h_panel_order != (rl ? 1 : 0)) {
+    // the kernel choice changed (NMF_H_KERNEL): the other order's entries go
+    const hipError_t e = hipMemsetAsync(p->panel_h, 0, p->panel_h_floats * sizeof(float), p->stream);
+    if (e != hipSuccess) return fail(NMF_E_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+  }
+  p->h_panel_order = rl ? 1 : 0;
+  TIMED(p, NMF_STEP_GRAM_S, gram(p, p->W, p->V, p->S, 1, rl));  // + the H update's panels
   TIMED(p, NMF_STEP_PRODUCT_R, product_R(p));
   HalsArgs a{};
   a.X = p->Ht;
@@ -427,7 +435,7 @@ int half_h(nmf_plan_s* p) {
   a.diag_one = 1;
   a.panel = p->panel_h;
   a.tile = p->h_tile;
-  a.cus = p->cus;
+  a.rows_layout = rl;
   TIMED(p, NMF_STEP_UPDATE_H, hals_update(a, p->stream));
   p->pq_valid = false;
   return NMF_OK;

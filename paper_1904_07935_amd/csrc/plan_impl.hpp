@@ -75,6 +75,7 @@ struct nmf_plan_s {
   float* c_top = nullptr;       // [n_top, K] their rows of P
   int32_t* top_idx = nullptr;   // [n_top] their row indices
   int n_top = 0;
+  int h_panel_order = -1;       // order of panel_h's entries: -1 all zero, 0 plain, 1 rows kernel's
   float* P = nullptr;
   float* Q = nullptr;
   float* R = nullptr;
@@ -112,7 +113,8 @@ struct nmf_plan_s {
 namespace plnmf {
 // out = X^T X; with panel_diag 1 also the H update's tile panels (p->panel_h,
 // p->h_tile wide), with 0 the W update's (p->panel, 32 wide)
-hipError_t gram(nmf_plan_s* p, const float* X, int64_t rows, float* out, int panel_diag = -1);
+hipError_t gram(nmf_plan_s* p, const float* X, int64_t rows, float* out, int panel_diag = -1,
+                bool rows_layout = false);
 int enqueue_objective(nmf_plan_s* p);
 // nmf_foldin on a given workspace (also serves the entry point that brings none)
 int foldin_run(nmf_plan p, const nmf_matrix* AnewT, float* Ht_new, int init_mode,
