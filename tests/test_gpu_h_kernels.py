@@ -41,6 +41,30 @@ def test_h_half_both_kernels_match_oracle(cuda, monkeypatch, V, D, K):
     assert rel_fro(got["rows"], got["lds"]) < 1e-4
 
 
+@pytest.mark.parametrize("K", [40, 200])
+def test_kernel_change_within_one_plan(cuda, monkeypatch, K):
+    """The two kernels read the Gram's panels in different orders; a plan whose
+    kernel choice changes between H halves (NMF_H_KERNEL) clears the other
+    order's entries first.  Three halves, rows -> lds -> rows, each against the
+    oracle's H half from the previous result."""
+    V, D = 300, 1000
+    A = datagen.dense_planted_uniform(V, D, K // 2, 0.01, seed=D + K + 1)
+    W0, H0 = datagen.uniform_init(V, D, K, seed=K + 3)
+    Ao = oracle_A(A)
+    Wn = hals.normalize_columns(W0)
+    plan = gpu_plan(A, W0, H0, cuda)
+    H = H0.astype(np.float64)
+    for kern in ("rows", "lds", "rows"):
+        monkeypatch.setenv("NMF_H_KERNEL", kern)
+        plan.half("H")
+        H, _, _ = hals.h_half(Ao, Wn, H, EPS)
+        got = _np(plan.Ht).T
+        assert rel_fro(got, H) < 1e-4, kern
+        assert row_rms_max(got, H) < 2e-4, kern
+        H = got.astype(np.float64)  # the next half starts where the GPU is
+    plan.close()
+
+
 def test_rows_kernel_full_sweeps_match_oracle(cuda, monkeypatch):
     """Ten sweeps of a sparse corpus with the rows kernel forced: the per-sweep
     objective bar of the FP32 path."""
